@@ -1,0 +1,466 @@
+/*
+ * mls_oracle.c -- plain FP64 CPU oracle for the moving-least-squares (MLS)
+ * projection of a point cloud.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. The product (the HIP
+ * library under paper_2401_03365_amd/) never links, loads or calls it, and
+ * this file shares no code, header, table or constant generator with it.
+ *
+ * What it computes (one query r against a cloud P = {p_i}):
+ *   O1  key(i, r) = ((dx*dx + dy*dy) + dz*dz), d = p_i - r, every operation a
+ *       binary64 round-to-nearest with no fused multiply-add (this file must be
+ *       compiled with -ffp-contract=off).
+ *   O2  N(r) = the k smallest (key, original index) pairs over the whole cloud,
+ *       brute force. Neighbourhood search replaces the paper's radius-R k-d
+ *       tree query (Section 2 introduction, Section 2.2) by k nearest
+ *       neighbours; ties go to the smaller index so the set is unique.
+ *   O3  support m = #{i in N(r) : key <= (3h)^2}; m < 3 -> OUTLIER, out = r
+ *       (Section 3.3: points with fewer than 3 neighbours are outliers).
+ *   O4  d_i = (p_i - r)/h, w_i = exp(-|d_i|^2) (Gaussian theta, positive and
+ *       monotonically decreasing as Section 1.4 requires), S0 = sum w_i,
+ *       mu = sum w_i d_i / S0, C = sum w_i d_i d_i^T / S0 - mu mu^T.
+ *   O5  n = unit eigenvector of the smallest eigenvalue of C (cyclic Jacobi).
+ *       This is the minimiser of Eq. (1.1) over |n| = 1 and D for the weights
+ *       taken at r (the one-step t = 0 form of the reference plane).
+ *   O6  plane H through r + h*mu with normal n; its origin q is the orthogonal
+ *       projection of r onto H: q = r + h <n, mu> n (Section 2.1: the
+ *       projection of the point onto H defines the origin q).
+ *   O7  orthonormal frame (u, v) on H (Section 1.4): u = normalize(e_a x n)
+ *       with a the axis of smallest |n_a| (lowest index on ties), v = n x u.
+ *   O8  e_i = (p_i - q)/h, x = <u,e>, y = <v,e>, f = <n,e>,
+ *       w'_i = exp(-|e_i|^2) (weights as a function of the distance from p_i
+ *       to q, as Section 1.4 states for the reference plane).
+ *   O9  weighted least squares fit of the heights f over H by the full
+ *       bivariate quadratic g(x,y) = a . phi, phi = (1, x, y, x^2, xy, y^2):
+ *       M = sum w' phi phi^T, b = sum w' f phi, Cholesky M = L L^T; the fit is
+ *       full only if m >= 6 and every pivot L_jj^2 > 1e-12 * max_j M_jj,
+ *       otherwise status PLANE_ONLY and out = q (Section 2.1: local polynomial
+ *       approximation g of the heights over H).
+ *   O10 out = q + h * g(0,0) * n = q + h a_0 n (Section 2.1 and Algorithm 1:
+ *       the projection of the point onto g is the result).
+ *   O12 gradient of out with respect to r and to the neighbours' positions,
+ *       neighbour lists and statuses held fixed, by central finite differences
+ *       with step 1e-6 * h.
+ *
+ * Input coordinates are doubles (FP32 data promoted exactly by the caller).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PT_OK 0
+#define ORC_PT_OUTLIER 1
+#define ORC_PT_PLANE_ONLY 2
+#define ORC_PT_NONFINITE 3
+#define ORC_PT_FLAG_AMBIGUOUS 0x10
+
+/* Diagnostics written per query when the caller asks for them. */
+#define ORC_DIAG 24
+/* [0..2] n, [3..5] eigenvalues ascending, [6..8] q, [9..11] u, [12..14] v,
+ * [15..20] a (coefficients of 1, x, y, x^2, xy, y^2), [21] support m,
+ * [22] S0, [23] min over j of L_jj^2 / max_j M_jj. */
+
+int orc_diag_stride(void) { return ORC_DIAG; }
+
+/* O1: canonical squared distance. */
+static double key3(const double *p, const double *r) {
+  double dx = p[0] - r[0];
+  double dy = p[1] - r[1];
+  double dz = p[2] - r[2];
+  double sx = dx * dx;
+  double sy = dy * dy;
+  double sz = dz * dz;
+  return (sx + sy) + sz;
+}
+
+static int finite3(const double *p) {
+  return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
+}
+
+/* (ka, ia) < (kb, ib) in the lexicographic order of O2. */
+static int pair_less(double ka, int64_t ia, double kb, int64_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+/* O2 for one query: brute force over the whole cloud. Keeps the k smallest
+ * pairs seen so far in ascending order (insertion), which equals sorting all
+ * n pairs and taking the first k. Returns the number of entries found (< k
+ * only when the cloud has fewer than k finite points). */
+static int knn_one(const double *P, int64_t n, const double *r, int k,
+                   int32_t *idx, double *key) {
+  int cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double *p = P + 3 * i;
+    if (!finite3(p)) continue;
+    double kk = key3(p, r);
+    if (cnt == k && !pair_less(kk, i, key[k - 1], idx[k - 1])) continue;
+    int j = (cnt < k) ? cnt : k - 1;
+    while (j > 0 && pair_less(kk, i, key[j - 1], idx[j - 1])) {
+      key[j] = key[j - 1];
+      idx[j] = idx[j - 1];
+      --j;
+    }
+    key[j] = kk;
+    idx[j] = (int32_t)i;
+    if (cnt < k) ++cnt;
+  }
+  return cnt;
+}
+
+/* Exported kNN: nbr and nbr_key are m x k, row-major. Non-finite queries and
+ * missing entries get index -1 and key NaN. */
+int orc_knn(const double *P, int64_t n, const double *Q, int64_t m, int32_t k,
+            int32_t *nbr, double *nbr_key) {
+  if (k <= 0) return 1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < m; ++j) {
+    int32_t *idx = nbr + j * k;
+    double *key = nbr_key + j * k;
+    int found = 0;
+    if (finite3(Q + 3 * j)) found = knn_one(P, n, Q + 3 * j, k, idx, key);
+    for (int t = found; t < k; ++t) {
+      idx[t] = -1;
+      key[t] = NAN;
+    }
+  }
+  return 0;
+}
+
+/* O5: cyclic Jacobi on a symmetric 3x3 matrix. On return lam is ascending and
+ * column c of V is the unit eigenvector of lam[c]. */
+static void jacobi3(double A[3][3], double V[3][3], double lam[3]) {
+  static const int PQ[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    double fro = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) fro += A[i][j] * A[i][j];
+    if (off <= 1e-30 * fro) break; /* sqrt(off) <= 1e-15 * |A|_F */
+    for (int t = 0; t < 3; ++t) {
+      int p = PQ[t][0], q = PQ[t][1];
+      double apq = A[p][q];
+      if (apq == 0.0) continue;
+      double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+      double tt;
+      if (fabs(theta) > 1e150)
+        tt = 0.5 / theta;
+      else
+        tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      double c = 1.0 / sqrt(tt * tt + 1.0);
+      double s = tt * c;
+      for (int i = 0; i < 3; ++i) { /* columns p, q of A */
+        double aip = A[i][p], aiq = A[i][q];
+        A[i][p] = c * aip - s * aiq;
+        A[i][q] = s * aip + c * aiq;
+      }
+      for (int i = 0; i < 3; ++i) { /* rows p, q of A */
+        double api = A[p][i], aqi = A[q][i];
+        A[p][i] = c * api - s * aqi;
+        A[q][i] = s * api + c * aqi;
+      }
+      A[p][q] = 0.0;
+      A[q][p] = 0.0;
+      for (int i = 0; i < 3; ++i) { /* columns p, q of V */
+        double vip = V[i][p], viq = V[i][q];
+        V[i][p] = c * vip - s * viq;
+        V[i][q] = s * vip + c * viq;
+      }
+    }
+  }
+  for (int i = 0; i < 3; ++i) lam[i] = A[i][i];
+  /* sort ascending, carrying the eigenvector columns */
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2 - a; ++b)
+      if (lam[b + 1] < lam[b]) {
+        double tl = lam[b];
+        lam[b] = lam[b + 1];
+        lam[b + 1] = tl;
+        for (int i = 0; i < 3; ++i) {
+          double tv = V[i][b];
+          V[i][b] = V[i][b + 1];
+          V[i][b + 1] = tv;
+        }
+      }
+}
+
+static void cross3(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double *a, const double *b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+typedef struct {
+  double support_radius_h; /* O3 radius in units of h (3) */
+  int min_support;         /* O3 minimum support (3) */
+  int min_support_fit;     /* O9 minimum support for the quadratic (6) */
+  double pivot_tol;        /* O9 relative Cholesky pivot tolerance (1e-12) */
+  double ambig_gap;        /* O5 relative eigen-gap for the flag (1e-6) */
+} orc_consts;
+
+/* O3-O10 for one query with a fixed neighbour list nb[0..k). */
+static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
+                           int k, double h, const orc_consts *cs, double *out,
+                           double *dg) {
+  if (dg)
+    for (int t = 0; t < ORC_DIAG; ++t) dg[t] = NAN;
+  if (!finite3(r)) {
+    out[0] = out[1] = out[2] = NAN;
+    return ORC_PT_NONFINITE;
+  }
+  for (int j = 0; j < k; ++j)
+    if (nb[j] < 0) {
+      out[0] = r[0];
+      out[1] = r[1];
+      out[2] = r[2];
+      return ORC_PT_OUTLIER;
+    }
+
+  /* O3: support within support_radius_h * h, compared on O1 keys */
+  double rad = cs->support_radius_h * h;
+  double rad2 = rad * rad;
+  int msup = 0;
+  for (int j = 0; j < k; ++j)
+    if (key3(P + 3 * (int64_t)nb[j], r) <= rad2) ++msup;
+  if (dg) dg[21] = msup;
+  if (msup < cs->min_support) {
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = r[2];
+    return ORC_PT_OUTLIER;
+  }
+
+  /* O4: weighted first and second moments about r in units of h */
+  double S0 = 0.0, S1[3] = {0, 0, 0}, S2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = 0; j < k; ++j) {
+    const double *p = P + 3 * (int64_t)nb[j];
+    double d[3] = {(p[0] - r[0]) / h, (p[1] - r[1]) / h, (p[2] - r[2]) / h};
+    double w = exp(-dot3(d, d));
+    S0 += w;
+    for (int a = 0; a < 3; ++a) {
+      S1[a] += w * d[a];
+      for (int b = 0; b < 3; ++b) S2[a][b] += w * d[a] * d[b];
+    }
+  }
+  double mu[3] = {S1[0] / S0, S1[1] / S0, S1[2] / S0};
+  double C[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C[a][b] = S2[a][b] / S0 - mu[a] * mu[b];
+
+  /* O5 */
+  double V[3][3], lam[3];
+  jacobi3(C, V, lam);
+  double nrm[3] = {V[0][0], V[1][0], V[2][0]};
+  double nn = sqrt(dot3(nrm, nrm));
+  for (int a = 0; a < 3; ++a) nrm[a] /= nn;
+  uint8_t flags = 0;
+  if (lam[1] - lam[0] < cs->ambig_gap * lam[2]) flags |= ORC_PT_FLAG_AMBIGUOUS;
+
+  /* O6 */
+  double t = dot3(nrm, mu);
+  double q[3] = {r[0] + h * t * nrm[0], r[1] + h * t * nrm[1], r[2] + h * t * nrm[2]};
+
+  /* O7 */
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (fabs(nrm[a]) < fabs(nrm[ax])) ax = a;
+  double ea[3] = {0, 0, 0};
+  ea[ax] = 1.0;
+  double u[3], v[3];
+  cross3(ea, nrm, u);
+  double un = sqrt(dot3(u, u));
+  for (int a = 0; a < 3; ++a) u[a] /= un;
+  cross3(nrm, u, v);
+
+  if (dg) {
+    for (int a = 0; a < 3; ++a) {
+      dg[0 + a] = nrm[a];
+      dg[3 + a] = lam[a];
+      dg[6 + a] = q[a];
+      dg[9 + a] = u[a];
+      dg[12 + a] = v[a];
+    }
+    dg[22] = S0;
+  }
+
+  /* O8, O9: weighted normal equations of the quadratic height fit */
+  double M[6][6], b[6];
+  memset(M, 0, sizeof M);
+  memset(b, 0, sizeof b);
+  for (int j = 0; j < k; ++j) {
+    const double *p = P + 3 * (int64_t)nb[j];
+    double e[3] = {(p[0] - q[0]) / h, (p[1] - q[1]) / h, (p[2] - q[2]) / h};
+    double x = dot3(u, e), y = dot3(v, e), f = dot3(nrm, e);
+    double w = exp(-dot3(e, e));
+    double phi[6] = {1.0, x, y, x * x, x * y, y * y};
+    for (int a = 0; a < 6; ++a) {
+      b[a] += w * f * phi[a];
+      for (int c = 0; c < 6; ++c) M[a][c] += w * phi[a] * phi[c];
+    }
+  }
+
+  double maxdiag = 0.0;
+  for (int a = 0; a < 6; ++a)
+    if (M[a][a] > maxdiag) maxdiag = M[a][a];
+  double L[6][6];
+  memset(L, 0, sizeof L);
+  int full = (msup >= cs->min_support_fit);
+  double minpiv = INFINITY;
+  for (int jj = 0; jj < 6 && full; ++jj) {
+    double s = M[jj][jj];
+    for (int c = 0; c < jj; ++c) s -= L[jj][c] * L[jj][c];
+    double rel = s / maxdiag;
+    if (rel < minpiv) minpiv = rel;
+    if (!(s > cs->pivot_tol * maxdiag)) {
+      full = 0;
+      break;
+    }
+    L[jj][jj] = sqrt(s);
+    for (int i = jj + 1; i < 6; ++i) {
+      double z = M[i][jj];
+      for (int c = 0; c < jj; ++c) z -= L[i][c] * L[jj][c];
+      L[i][jj] = z / L[jj][jj];
+    }
+  }
+  if (dg) dg[23] = minpiv;
+  if (!full) {
+    out[0] = q[0];
+    out[1] = q[1];
+    out[2] = q[2];
+    return ORC_PT_PLANE_ONLY | flags;
+  }
+  double y6[6], a6[6];
+  for (int i = 0; i < 6; ++i) {
+    double z = b[i];
+    for (int c = 0; c < i; ++c) z -= L[i][c] * y6[c];
+    y6[i] = z / L[i][i];
+  }
+  for (int i = 5; i >= 0; --i) {
+    double z = y6[i];
+    for (int c = i + 1; c < 6; ++c) z -= L[c][i] * a6[c];
+    a6[i] = z / L[i][i];
+  }
+  if (dg)
+    for (int a = 0; a < 6; ++a) dg[15 + a] = a6[a];
+
+  /* O10 */
+  for (int a = 0; a < 3; ++a) out[a] = q[a] + h * a6[0] * nrm[a];
+  return ORC_PT_OK | flags;
+}
+
+static void fill_consts(orc_consts *cs, double support_radius_h, int min_support) {
+  cs->support_radius_h = support_radius_h;
+  cs->min_support = min_support;
+  cs->min_support_fit = 6;
+  cs->pivot_tol = 1e-12;
+  cs->ambig_gap = 1e-6;
+}
+
+/* Exported projection with given neighbour lists (m x k original indices). */
+int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
+                int32_t k, double h, const int32_t *nbr,
+                double support_radius_h, int32_t min_support, double *out,
+                uint8_t *status, double *diag) {
+  (void)n;
+  if (k <= 0 || !(h > 0.0) || !isfinite(h)) return 1;
+  orc_consts cs;
+  fill_consts(&cs, support_radius_h, min_support);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t j = 0; j < m; ++j) {
+    status[j] = project_one(P, Q + 3 * j, nbr + j * k, k, h, &cs, out + 3 * j,
+                            diag ? diag + ORC_DIAG * j : NULL);
+  }
+  return 0;
+}
+
+/* O12: J^T g by central finite differences, lists and statuses fixed.
+ * gq (m x 3) receives d<g_j, out_j>/d r_j; gp (n x 3) accumulates
+ * sum_j d<g_j, out_j>/d p_i over the queries j whose list holds i. Queries
+ * whose status is not OK contribute their exact derivative where it is
+ * trivial (OUTLIER: identity in r) and are otherwise differenced as well. */
+int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
+                int32_t k, double h, const int32_t *nbr, double support_radius_h,
+                int32_t min_support, const double *gout, double rel_step,
+                double *gq, double *gp) {
+  if (k <= 0 || !(h > 0.0)) return 1;
+  orc_consts cs;
+  fill_consts(&cs, support_radius_h, min_support);
+  memset(gp, 0, sizeof(double) * 3 * (size_t)n);
+  double step = rel_step * h;
+  int nthr_fail = 0;
+#pragma omp parallel
+  {
+    double *Pl = (double *)malloc(sizeof(double) * 3 * (size_t)(k + 1));
+    double *gl = (double *)malloc(sizeof(double) * 3 * (size_t)k);
+    int32_t *loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    if (!Pl || !gl || !loc) {
+#pragma omp atomic write
+      nthr_fail = 1;
+    }
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t j = 0; j < m; ++j) {
+      if (!Pl || !gl || !loc) continue;
+      const int32_t *nb = nbr + j * k;
+      const double *g = gout + 3 * j;
+      double r[3] = {Q[3 * j], Q[3 * j + 1], Q[3 * j + 2]};
+      double o0[3];
+      uint8_t s0 = project_one(P, r, nb, k, h, &cs, o0, NULL);
+      for (int a = 0; a < 3 * k; ++a) gl[a] = 0.0;
+      /* local copy of the neighbour coordinates, indexed 0..k-1 */
+      for (int t = 0; t < k; ++t) {
+        loc[t] = t;
+        for (int a = 0; a < 3; ++a) Pl[3 * t + a] = nb[t] >= 0 ? P[3 * (int64_t)nb[t] + a] : 0.0;
+      }
+      if ((s0 & 0x0f) == ORC_PT_NONFINITE) {
+        gq[3 * j] = gq[3 * j + 1] = gq[3 * j + 2] = 0.0;
+        continue;
+      }
+      if ((s0 & 0x0f) == ORC_PT_OUTLIER) {
+        gq[3 * j] = g[0];
+        gq[3 * j + 1] = g[1];
+        gq[3 * j + 2] = g[2];
+        continue;
+      }
+      double op[3], om[3];
+      for (int a = 0; a < 3; ++a) {
+        double rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]};
+        rp[a] += step;
+        rm[a] -= step;
+        project_one(Pl, rp, loc, k, h, &cs, op, NULL);
+        project_one(Pl, rm, loc, k, h, &cs, om, NULL);
+        gq[3 * j + a] = (g[0] * (op[0] - om[0]) + g[1] * (op[1] - om[1]) +
+                         g[2] * (op[2] - om[2])) / (2.0 * step);
+      }
+      for (int t = 0; t < k; ++t) {
+        for (int a = 0; a < 3; ++a) {
+          double keep = Pl[3 * t + a];
+          Pl[3 * t + a] = keep + step;
+          project_one(Pl, r, loc, k, h, &cs, op, NULL);
+          Pl[3 * t + a] = keep - step;
+          project_one(Pl, r, loc, k, h, &cs, om, NULL);
+          Pl[3 * t + a] = keep;
+          gl[3 * t + a] = (g[0] * (op[0] - om[0]) + g[1] * (op[1] - om[1]) +
+                           g[2] * (op[2] - om[2])) / (2.0 * step);
+        }
+      }
+      for (int t = 0; t < k; ++t) {
+        if (nb[t] < 0) continue;
+        for (int a = 0; a < 3; ++a) {
+#pragma omp atomic
+          gp[3 * (int64_t)nb[t] + a] += gl[3 * t + a];
+        }
+      }
+    }
+    free(Pl);
+    free(gl);
+    free(loc);
+  }
+  return nthr_fail ? 2 : 0;
+}
