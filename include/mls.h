@@ -1,0 +1,226 @@
+/*
+ * mls.h -- C ABI of the MI355X (gfx950) moving-least-squares projection
+ * library (libmls.so).
+ *
+ * The operation: given a point cloud P = {p_i} sampled (with noise) from a
+ * surface, project query points r near the surface onto the MLS surface of P
+ * (Section 1.4, problem statement; Algorithm 1: input a point set, output a
+ * surface represented by a point set). For every query the library
+ *   1. finds the k nearest cloud points exactly (canonical FP64 squared
+ *      distances, ties to the smaller original index) from a Morton-sorted
+ *      uniform grid hash -- the neighbourhood search of Section 2 and
+ *      Section 2.2, with k neighbours instead of a radius;
+ *   2. weights them with theta(d) = exp(-d^2/h^2) (Section 1.4 asks for a
+ *      smooth, positive, monotonically decreasing theta);
+ *   3. fits the reference plane H (Eq. (1.1), one step with the weights
+ *      centred at r): n = eigenvector of the smallest eigenvalue of the
+ *      weighted 3x3 covariance; origin q = orthogonal projection of r on H;
+ *   4. fits the heights over H with a weighted bivariate quadratic g in an
+ *      orthonormal frame of H with origin q, weights theta(|p_i - q|)
+ *      (Section 2.1, Algorithm 1);
+ *   5. returns q + g(0,0) n, the projection of the point onto g
+ *      (Section 2.1, Algorithm 1).
+ * A query with fewer than `min_support` list entries within
+ * `support_radius_h * h` is an outlier (Section 3.3) and is returned
+ * unchanged with status MLS_PT_OUTLIER.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless marked (host). The caller
+ *     owns every array and every workspace; the library allocates no device
+ *     memory of its own.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Calls are stream-ordered. mls_build_grid synchronises `stream` twice
+ *     (to size the grid); the other calls never block the host.
+ *   - Argument errors are found on the host before anything is launched and
+ *     are returned as codes; nothing aborts and no exception crosses the ABI.
+ *     A failed launch or an earlier asynchronous device error is returned as
+ *     MLS_ERR_HIP (the HIP error text is kept by mls_last_error()).
+ *   - Per-point conditions are statuses, not errors (MLS_PT_*).
+ *   - Points are FP32 xyz triples (n_points x 3, row-major). Queries and
+ *     outputs are FP32 or FP64 triples (dtype).
+ */
+#ifndef MLS_H
+#define MLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLS_OK = 0,
+  MLS_ERR_INVALID_ARGUMENT = 1,
+  MLS_ERR_TOO_FEW_POINTS = 2,
+  MLS_ERR_UNSUPPORTED = 3,
+  MLS_ERR_WORKSPACE_TOO_SMALL = 4,
+  MLS_ERR_OUT_OF_MEMORY = 5,
+  MLS_ERR_HIP = 6
+} mls_status;
+
+typedef enum { MLS_F32 = 0, MLS_F64 = 1 } mls_dtype;
+
+typedef enum {
+  MLS_PREC_FP64 = 0,        /* moments, eigen-solve and Cholesky in FP64 */
+  MLS_PREC_FP32_MOMENTS = 1 /* moments in FP32 on centred, h-scaled
+                               coordinates with compensated block sums;
+                               eigen-solve and Cholesky in FP64 */
+} mls_precision;
+
+/* Per-point status byte: low nibble is the status, bit 4 a flag. */
+enum {
+  MLS_PT_OK = 0,         /* projected onto the local quadratic */
+  MLS_PT_OUTLIER = 1,    /* fewer than min_support neighbours within
+                            support_radius_h * h (Section 3.3); out = r */
+  MLS_PT_PLANE_ONLY = 2, /* quadratic fit singular (support < 6 or a
+                            Cholesky pivot <= 1e-12 * max diagonal); out = q */
+  MLS_PT_NONFINITE = 3,  /* query has a NaN/Inf coordinate; out = NaN */
+  MLS_PT_FLAG_NORMAL_AMBIGUOUS = 0x10 /* lambda2 - lambda1 < 1e-6 lambda3 */
+};
+
+#define MLS_MAX_K 64
+
+typedef struct mls_grid mls_grid; /* opaque, host-side handle */
+
+/* Projection parameters (host struct). */
+typedef struct {
+  int32_t k;                /* neighbours per query, 1 <= k <= MLS_MAX_K and
+                               k <= finite points of every cloud */
+  int32_t precision;        /* mls_precision */
+  double support_radius_h;  /* outlier radius in units of h (default 3.0) */
+  int32_t min_support;      /* outlier threshold (default 3) */
+  int32_t reserved;         /* must be 0 */
+} mls_params;
+
+/* Library version string (host). */
+const char *mls_version(void);
+/* Text of a status code (host). */
+const char *mls_status_string(mls_status s);
+/* Text of the last HIP error seen by this thread ("" if none) (host). */
+const char *mls_last_error(void);
+
+/* ---- grid --------------------------------------------------------------
+ * The grid is the spatial index of the cloud: points sorted by
+ * (cloud, Morton code of their uniform-grid cell) -- Morton order is the
+ * reordering the paper suggests for chaotic clouds (Section 2 introduction)
+ * -- plus an open-addressing hash from cell to its contiguous range of
+ * sorted points. It replaces the paper's per-process k-d tree (Section 2.2).
+ *
+ * Bytes of device workspace mls_build_grid needs for n_points points in
+ * n_clouds clouds (host). */
+size_t mls_grid_workspace_bytes(int64_t n_points, int32_t n_clouds);
+
+/* Build the grid of one cloud or of a batch of clouds.
+ *   points          n_points x 3 FP32 (device). Copied into the workspace
+ *                   (Morton-sorted snapshot): later writes to `points` do not
+ *                   affect the grid. Points with a NaN/Inf coordinate are kept
+ *                   out of every neighbourhood.
+ *   cloud_offsets   (host) n_clouds+1 ascending offsets into points, first 0,
+ *                   last n_points; NULL means one cloud.
+ *   h               (host) n_clouds Gaussian widths, finite and > 0.
+ *   cell_size       (host) n_clouds cell edges, or NULL; entries <= 0 select
+ *                   3h. The edge grows when a cloud would need more than
+ *                   2^21 cells along an axis.
+ *   workspace       device buffer of at least mls_grid_workspace_bytes(),
+ *                   256-byte aligned; it holds the grid and must outlive it.
+ *   out_grid        (host) receives the handle.
+ * Errors: INVALID_ARGUMENT (null pointers, n_points < 1, n_clouds < 1,
+ * offsets not ascending or not spanning the points, h not finite and > 0,
+ * misaligned workspace), WORKSPACE_TOO_SMALL, OUT_OF_MEMORY (host handle),
+ * HIP. */
+mls_status mls_build_grid(const float *points, int64_t n_points,
+                          const int64_t *cloud_offsets, int32_t n_clouds,
+                          const double *h, const double *cell_size,
+                          void *workspace, size_t workspace_bytes, void *stream,
+                          mls_grid **out_grid);
+
+/* Frees the host handle only (the workspace is the caller's). */
+mls_status mls_grid_destroy(mls_grid *grid);
+
+/* Host-visible facts about a built grid (host). */
+typedef struct {
+  int64_t n_points;
+  int32_t n_clouds;
+  int32_t key_bits;       /* bits of the (cloud, Morton) sort key */
+  int64_t n_cells;        /* non-empty cells over all clouds */
+  int64_t hash_capacity;  /* slots of the cell hash */
+  int64_t n_nonfinite;    /* points left out of every neighbourhood */
+  int64_t min_cloud_finite; /* smallest number of finite points in a cloud */
+} mls_grid_info;
+mls_status mls_get_grid_info(const mls_grid *grid, mls_grid_info *info);
+
+/* Per-cloud geometry the grid chose (host): origin xyz, cell edge, dims xyz
+ * for cloud c. */
+mls_status mls_get_cloud_grid(const mls_grid *grid, int32_t c, double origin[3],
+                              double *cell, int32_t dims[3]);
+
+/* Sorted-order view of the grid (device pointers into the workspace, for the
+ * caller's inspection): xyzw with w = original index bits, and the inverse
+ * permutation (original index -> sorted position). */
+mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
+                                  const int32_t **inverse_perm);
+
+/* ---- projection --------------------------------------------------------
+ * Queries belong to clouds. query_offsets (host, n_clouds+1, ascending,
+ * spanning n_queries) gives each cloud's contiguous query range; NULL means
+ * the queries are aligned with the grid's points (n_queries == n_points,
+ * query i belongs to the cloud of point i) or, for one cloud, that every
+ * query belongs to it.
+ *
+ * Bytes of device workspace mls_project / mls_knn / mls_project_backward
+ * need for n_queries queries with k neighbours (host). */
+size_t mls_project_workspace_bytes(const mls_grid *grid, int32_t k,
+                                   int64_t n_queries);
+
+/* Exact k nearest neighbours of each query (step 1 alone).
+ *   out_neighbors  n_queries x k int32 ORIGINAL point indices, ascending by
+ *                  (FP64 squared distance, index); -1 pads a list when the
+ *                  cloud has fewer than k finite points and for non-finite
+ *                  queries.
+ *   out_keys       nullable, n_queries x k FP64 squared distances. */
+mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries,
+                   mls_dtype dtype, int64_t n_queries,
+                   const int64_t *query_offsets, int32_t *out_neighbors,
+                   double *out_keys, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/* One MLS projection pass (steps 1-5) of every query.
+ *   out_points     n_queries x 3 in `dtype` (may alias `queries`: each output
+ *                  is written after its own query has been read and no query
+ *                  reads another query).
+ *   out_status     n_queries status bytes (MLS_PT_*).
+ *   out_neighbors  nullable; as in mls_knn. Keep it to run the backward pass
+ *                  without recomputing the lists.
+ * Iterated passes (the surface is approached by moving the queries) call this
+ * again with the outputs as queries and the same grid. */
+mls_status mls_project(const mls_grid *grid, const mls_params *params,
+                       const void *queries, mls_dtype dtype, int64_t n_queries,
+                       const int64_t *query_offsets, void *out_points,
+                       uint8_t *out_status, int32_t *out_neighbors,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* Adjoint of mls_project with respect to the query and point positions, with
+ * the neighbour lists and statuses of the forward pass held fixed and every
+ * per-query moment recomputed.
+ *   neighbors      n_queries x k lists from mls_project (ORIGINAL indices),
+ *                  or NULL to recompute them bit-exactly.
+ *   grad_out       n_queries x 3 in `dtype`: dL/d out.
+ *   grad_queries   n_queries x 3 in `dtype`, overwritten with dL/d r.
+ *   grad_points    n_points x 3 FP32 or FP64 (`dtype`), overwritten with
+ *                  dL/d p (sum over every query that has the point in its
+ *                  list).
+ * When the queries are the cloud's own points, the gradient with respect to
+ * the cloud is grad_queries + grad_points. */
+mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
+                                const void *queries, mls_dtype dtype,
+                                int64_t n_queries, const int64_t *query_offsets,
+                                const int32_t *neighbors, const void *grad_out,
+                                void *grad_queries, void *grad_points,
+                                void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLS_H */

@@ -1,0 +1,237 @@
+"""PyTorch-facing binding of libmls.so.
+
+PyTorch provides device memory (tensors, workspaces) and the current HIP
+stream; every step of the projection runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+
+PRECISIONS = {"fp64": _abi.MLS_PREC_FP64, "fp32": _abi.MLS_PREC_FP32_MOMENTS}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _host_i64(a):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_points(t: torch.Tensor, name: str, dtypes=(torch.float32,)):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype not in dtypes or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous (n, 3) tensor of %s" % (name, dtypes))
+
+
+def _dtype_code(t: torch.Tensor):
+    return _abi.MLS_F64 if t.dtype == torch.float64 else _abi.MLS_F32
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Grid:
+    """Morton-sorted uniform-grid index of one cloud or a batch of clouds.
+
+    ``h`` is the Gaussian width per cloud; ``cell_size`` (per cloud, or None)
+    the grid cell edge (default 3h)."""
+
+    def __init__(self, points: torch.Tensor, h, cloud_offsets=None, cell_size=None):
+        lib = _abi.load()
+        _check_points(points, "points")
+        n = points.shape[0]
+        offs, offs_p = _host_i64(cloud_offsets)
+        n_clouds = 1 if offs is None else len(offs) - 1
+        hh = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (n_clouds,)))
+        cs = None
+        if cell_size is not None:
+            cs = np.ascontiguousarray(np.broadcast_to(np.asarray(cell_size, dtype=np.float64),
+                                                      (n_clouds,)))
+        nbytes = lib.mls_grid_workspace_bytes(n, n_clouds)
+        if nbytes == 0:
+            raise ValueError("invalid grid size")
+        self.points = points
+        self.device = points.device
+        self.n_points = n
+        self.n_clouds = n_clouds
+        self.h = hh
+        self.offsets = offs
+        self.workspace = _workspace(nbytes, points.device)
+        handle = ctypes.c_void_p()
+        code = lib.mls_build_grid(_ptr(points), n, offs_p, n_clouds,
+                                  hh.ctypes.data_as(ctypes.c_void_p),
+                                  cs.ctypes.data_as(ctypes.c_void_p) if cs is not None else None,
+                                  _ptr(self.workspace), self.workspace.numel(), _stream(),
+                                  ctypes.byref(handle))
+        _abi.check(code, "mls_build_grid")
+        self._handle = handle
+        self._proj_ws = None
+
+    # ---- facts ------------------------------------------------------------
+    def info(self) -> dict:
+        info = _abi.MlsGridInfo()
+        _abi.check(_abi.load().mls_get_grid_info(self._handle, ctypes.byref(info)),
+                   "mls_get_grid_info")
+        return {f: getattr(info, f) for f, _ in info._fields_}
+
+    def cloud_grid(self, c: int = 0):
+        origin = (ctypes.c_double * 3)()
+        cell = ctypes.c_double()
+        dims = (ctypes.c_int32 * 3)()
+        _abi.check(_abi.load().mls_get_cloud_grid(self._handle, c, origin, ctypes.byref(cell),
+                                                  dims), "mls_get_cloud_grid")
+        return list(origin), cell.value, list(dims)
+
+    def sorted_points(self):
+        """(xyzw float32 (n,4) view, inverse permutation int32 (n,)) of the grid."""
+        xyzw = ctypes.c_void_p()
+        inv = ctypes.c_void_p()
+        _abi.check(_abi.load().mls_grid_sorted_points(self._handle, ctypes.byref(xyzw),
+                                                      ctypes.byref(inv)), "mls_grid_sorted_points")
+        base = self.workspace.data_ptr()
+        o1 = xyzw.value - base
+        o2 = inv.value - base
+        pts = self.workspace[o1:o1 + 16 * self.n_points].view(torch.float32).view(-1, 4)
+        ip = self.workspace[o2:o2 + 4 * self.n_points].view(torch.int32)
+        return pts, ip
+
+    # ---- workspace --------------------------------------------------------
+    def _proj_workspace(self, k: int, n: int) -> torch.Tensor:
+        nbytes = _abi.load().mls_project_workspace_bytes(self._handle, k, n)
+        if nbytes == 0:
+            raise ValueError("invalid k or query count")
+        if self._proj_ws is None or self._proj_ws.numel() < nbytes:
+            self._proj_ws = _workspace(nbytes, self.device)
+        return self._proj_ws
+
+    # ---- calls ------------------------------------------------------------
+    def knn(self, queries: torch.Tensor, k: int, query_offsets=None, return_keys=False):
+        _check_points(queries, "queries", (torch.float32, torch.float64))
+        n = queries.shape[0]
+        nbr = torch.empty((n, k), dtype=torch.int32, device=self.device)
+        keys = torch.empty((n, k), dtype=torch.float64, device=self.device) if return_keys else None
+        ws = self._proj_workspace(k, n)
+        qo, qo_p = _host_i64(query_offsets)
+        code = _abi.load().mls_knn(self._handle, k, _ptr(queries), _dtype_code(queries), n, qo_p,
+                                   _ptr(nbr), _ptr(keys), _ptr(ws), ws.numel(), _stream())
+        _abi.check(code, "mls_knn")
+        return (nbr, keys) if return_keys else nbr
+
+    def _params(self, k, precision, support_radius_h, min_support):
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be 'fp32' or 'fp64'")
+        return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
+                              support_radius_h=float(support_radius_h),
+                              min_support=int(min_support), reserved=0)
+
+    def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
+                query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
+                support_radius_h: float = 3.0, min_support: int = 3):
+        """One MLS projection pass. Returns (out, status[, neighbours])."""
+        _check_points(queries, "queries", (torch.float32, torch.float64))
+        n = queries.shape[0]
+        params = self._params(k, precision, support_radius_h, min_support)
+        if out is None:
+            out = torch.empty_like(queries)
+        status = torch.empty((n,), dtype=torch.uint8, device=self.device)
+        nbr = torch.empty((n, k), dtype=torch.int32, device=self.device) if return_neighbors else None
+        ws = self._proj_workspace(k, n)
+        qo, qo_p = _host_i64(query_offsets)
+        code = _abi.load().mls_project(self._handle, ctypes.byref(params), _ptr(queries),
+                                       _dtype_code(queries), n, qo_p, _ptr(out), _ptr(status),
+                                       _ptr(nbr), _ptr(ws), ws.numel(), _stream())
+        _abi.check(code, "mls_project")
+        return (out, status, nbr) if return_neighbors else (out, status)
+
+    def project_backward(self, queries: torch.Tensor, grad_out: torch.Tensor, k: int,
+                         precision: str = "fp32", neighbors: Optional[torch.Tensor] = None,
+                         query_offsets=None, support_radius_h: float = 3.0, min_support: int = 3):
+        """Adjoint of one pass: returns (grad_queries, grad_points)."""
+        _check_points(queries, "queries", (torch.float32, torch.float64))
+        n = queries.shape[0]
+        params = self._params(k, precision, support_radius_h, min_support)
+        grad_out = grad_out.contiguous().to(queries.dtype)
+        gq = torch.empty_like(queries)
+        gp = torch.empty((self.n_points, 3), dtype=queries.dtype, device=self.device)
+        ws = self._proj_workspace(k, n)
+        qo, qo_p = _host_i64(query_offsets)
+        code = _abi.load().mls_project_backward(
+            self._handle, ctypes.byref(params), _ptr(queries), _dtype_code(queries), n, qo_p,
+            _ptr(neighbors.contiguous() if neighbors is not None else None), _ptr(grad_out),
+            _ptr(gq), _ptr(gp), _ptr(ws), ws.numel(), _stream())
+        _abi.check(code, "mls_project_backward")
+        return gq, gp
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _abi.load().mls_grid_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_grid(points, h, cloud_offsets=None, cell_size=None) -> Grid:
+    return Grid(points, h, cloud_offsets=cloud_offsets, cell_size=cell_size)
+
+
+def project(points: torch.Tensor, h, k: int, precision: str = "fp32", passes: int = 1,
+            cell_size=None, cloud_offsets=None):
+    """Project a cloud onto its own MLS surface ``passes`` times (queries move,
+    the cloud and its grid stay fixed). Returns (out, status)."""
+    grid = Grid(points, h, cloud_offsets=cloud_offsets, cell_size=cell_size)
+    cur = points
+    st = None
+    for _ in range(passes):
+        out, st_new = grid.project(cur, k, precision)
+        if st is not None:
+            frozen = (st & 0x0F) == _abi.PT_OUTLIER
+            out[frozen] = cur[frozen]
+            st_new = torch.where(frozen, st, st_new)
+        cur, st = out, st_new
+    return cur, st
+
+
+class MLSProject(torch.autograd.Function):
+    """out = P(queries; cloud) with a backward through the hand-written
+    adjoint kernel (lists held fixed, moments recomputed)."""
+
+    @staticmethod
+    def forward(ctx, queries, points, grid: Grid, k: int, precision: str):
+        out, status, nbr = grid.project(queries.detach().contiguous(), k, precision,
+                                        return_neighbors=True)
+        ctx.grid, ctx.k, ctx.precision = grid, k, precision
+        ctx.save_for_backward(queries.detach(), nbr)
+        ctx.mark_non_differentiable(status)
+        return out, status
+
+    @staticmethod
+    def backward(ctx, grad_out, grad_status):
+        queries, nbr = ctx.saved_tensors
+        gq, gp = ctx.grid.project_backward(queries, grad_out, ctx.k, ctx.precision, neighbors=nbr)
+        return gq, gp.to(queries.dtype), None, None, None
+
+
+def mls_project(queries, points, grid: Grid, k: int, precision: str = "fp32"):
+    """Differentiable projection; gradients flow to queries and points."""
+    return MLSProject.apply(queries, points, grid, k, precision)

@@ -1,0 +1,444 @@
+// abi.hip -- extern "C" entry points of libmls.so: argument validation on the
+// host, workspace carving, and the launch sequence of each call.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "mls_internal.h"
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+mls_status hip_fail(hipError_t e, const char *where) {
+  snprintf(g_last_error, sizeof g_last_error, "%s: %s", where, hipGetErrorString(e));
+  return MLS_ERR_HIP;
+}
+
+#define MLS_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Byte layout of the grid workspace.
+struct GridLayout {
+  size_t pts, inv_perm, keys_a, keys_b, vals_a, vals_b, radix, table, clouds, offsets, bbox,
+      nonfinite, counter, total;
+  uint64_t table_cap_max;
+};
+
+GridLayout grid_layout(int64_t n, int32_t c) {
+  GridLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  L.pts = take(16 * (size_t)n);
+  L.inv_perm = take(4 * (size_t)n);
+  L.keys_a = take(8 * (size_t)n);
+  L.keys_b = take(8 * (size_t)n);
+  L.vals_a = take(4 * (size_t)n);
+  L.vals_b = take(4 * (size_t)n);
+  L.radix = take(mls::radix_temp_bytes(n));
+  L.table_cap_max = next_pow2(std::max<uint64_t>(2 * (uint64_t)n, 64));
+  L.table = take(16 * L.table_cap_max);
+  L.clouds = take(sizeof(mls::CloudDev) * (size_t)c);
+  L.offsets = take(8 * ((size_t)c + 1));
+  L.bbox = take(24 * (size_t)c);
+  L.nonfinite = take(8 * (size_t)c);
+  L.counter = take(64);
+  L.total = o;
+  return L;
+}
+
+// Byte layout of the projection workspace.
+struct ProjLayout {
+  size_t nbr, support, qcloud, offsets, total;
+};
+
+ProjLayout proj_layout(int32_t n_clouds, int32_t k, int64_t n) {
+  ProjLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  L.nbr = take(4 * (size_t)n * (size_t)k);
+  L.support = take((size_t)n);
+  L.qcloud = take(n_clouds > 1 ? 4 * (size_t)n : 0);
+  L.offsets = take(8 * ((size_t)n_clouds + 1));
+  L.total = o;
+  return L;
+}
+
+bool offsets_ok(const int64_t *off, int32_t c, int64_t n) {
+  if (off[0] != 0 || off[c] != n) return false;
+  for (int32_t i = 0; i < c; ++i)
+    if (off[i + 1] < off[i]) return false;
+  return true;
+}
+
+float ordered_to_float(uint32_t o) {
+  uint32_t b = (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+
+mls_status check_async() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "earlier asynchronous error");
+  return MLS_OK;
+}
+
+}  // namespace
+
+struct mls_grid {
+  mls::GridHost g;
+};
+
+extern "C" {
+
+const char *mls_version(void) { return "mls-mi355x 0.1 (gfx950)"; }
+
+const char *mls_status_string(mls_status s) {
+  switch (s) {
+    case MLS_OK: return "ok";
+    case MLS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case MLS_ERR_TOO_FEW_POINTS: return "a cloud has fewer finite points than k";
+    case MLS_ERR_UNSUPPORTED: return "unsupported";
+    case MLS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case MLS_ERR_OUT_OF_MEMORY: return "out of host memory";
+    case MLS_ERR_HIP: return "HIP error";
+  }
+  return "unknown status";
+}
+
+const char *mls_last_error(void) { return g_last_error; }
+
+size_t mls_grid_workspace_bytes(int64_t n_points, int32_t n_clouds) {
+  if (n_points < 1 || n_clouds < 1) return 0;
+  return grid_layout(n_points, n_clouds).total;
+}
+
+mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *cloud_offsets,
+                          int32_t n_clouds, const double *h, const double *cell_size,
+                          void *workspace, size_t workspace_bytes, void *stream,
+                          mls_grid **out_grid) {
+  g_last_error[0] = 0;
+  if (!out_grid) return MLS_ERR_INVALID_ARGUMENT;
+  *out_grid = nullptr;
+  if (!points || !h || !workspace || n_points < 1 || n_clouds < 1 ||
+      n_points > 0x7fffffffll || n_clouds > 65535)
+    return MLS_ERR_INVALID_ARGUMENT;
+  if (((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
+  if (cloud_offsets ? !offsets_ok(cloud_offsets, n_clouds, n_points) : n_clouds != 1)
+    return MLS_ERR_INVALID_ARGUMENT;
+  for (int32_t c = 0; c < n_clouds; ++c) {
+    if (!(h[c] > 0.0) || !isfinite(h[c])) return MLS_ERR_INVALID_ARGUMENT;
+    if (cell_size && !isfinite(cell_size[c])) return MLS_ERR_INVALID_ARGUMENT;
+  }
+  const GridLayout L = grid_layout(n_points, n_clouds);
+  if (workspace_bytes < L.total) return MLS_ERR_WORKSPACE_TOO_SMALL;
+  mls_status st = check_async();
+  if (st != MLS_OK) return st;
+
+  mls_grid *G = new (std::nothrow) mls_grid();
+  if (!G) return MLS_ERR_OUT_OF_MEMORY;
+  mls::GridHost &gh = G->g;
+  gh.offsets = (int64_t *)malloc(8 * ((size_t)n_clouds + 1));
+  gh.finite_counts = (int64_t *)malloc(8 * (size_t)n_clouds);
+  gh.clouds_host = (mls::CloudDev *)calloc((size_t)n_clouds, sizeof(mls::CloudDev));
+  uint32_t *bbox_h = (uint32_t *)malloc(24 * (size_t)n_clouds);
+  unsigned long long *nonfin_h = (unsigned long long *)malloc(8 * (size_t)n_clouds);
+  auto cleanup = [&](mls_status s) {
+    free(bbox_h);
+    free(nonfin_h);
+    if (s != MLS_OK) {
+      free(gh.offsets);
+      free(gh.finite_counts);
+      free(gh.clouds_host);
+      delete G;
+    }
+    return s;
+  };
+  if (!gh.offsets || !gh.finite_counts || !gh.clouds_host || !bbox_h || !nonfin_h)
+    return cleanup(MLS_ERR_OUT_OF_MEMORY);
+  if (cloud_offsets) memcpy(gh.offsets, cloud_offsets, 8 * ((size_t)n_clouds + 1));
+  else { gh.offsets[0] = 0; gh.offsets[1] = n_points; }
+
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  float4 *pts = (float4 *)(ws + L.pts);
+  int32_t *inv_perm = (int32_t *)(ws + L.inv_perm);
+  uint64_t *keys_a = (uint64_t *)(ws + L.keys_a), *keys_b = (uint64_t *)(ws + L.keys_b);
+  int32_t *vals_a = (int32_t *)(ws + L.vals_a), *vals_b = (int32_t *)(ws + L.vals_b);
+  uint4 *table = (uint4 *)(ws + L.table);
+  mls::CloudDev *clouds = (mls::CloudDev *)(ws + L.clouds);
+  int64_t *offsets_dev = (int64_t *)(ws + L.offsets);
+  uint32_t *bbox = (uint32_t *)(ws + L.bbox);
+  unsigned long long *nonfin = (unsigned long long *)(ws + L.nonfinite);
+  unsigned long long *counter = (unsigned long long *)(ws + L.counter);
+
+  int64_t max_cloud = 0;
+  for (int32_t c = 0; c < n_clouds; ++c)
+    max_cloud = std::max(max_cloud, gh.offsets[c + 1] - gh.offsets[c]);
+
+  hipError_t e;
+#define STEP(call)                                         \
+  do {                                                     \
+    e = (call);                                            \
+    if (e != hipSuccess) return cleanup(hip_fail(e, #call)); \
+  } while (0)
+  STEP(hipMemcpyAsync(offsets_dev, gh.offsets, 8 * ((size_t)n_clouds + 1),
+                      hipMemcpyHostToDevice, s));
+  STEP(mls::launch_bbox(points, offsets_dev, n_clouds, max_cloud, bbox, nonfin, s));
+  STEP(hipMemcpyAsync(bbox_h, bbox, 24 * (size_t)n_clouds, hipMemcpyDeviceToHost, s));
+  STEP(hipMemcpyAsync(nonfin_h, nonfin, 8 * (size_t)n_clouds, hipMemcpyDeviceToHost, s));
+  STEP(hipStreamSynchronize(s));
+
+  // per-cloud geometry: origin at the box minimum, dims covering the box
+  int cloud_bits = 0;
+  while ((1ll << cloud_bits) < n_clouds) ++cloud_bits;
+  const int max_bits = std::min(21, (63 - cloud_bits) / 3);
+  int bits = 1;
+  int64_t sorted_at = 0, nonfinite_total = 0, min_finite = INT64_MAX;
+  for (int32_t c = 0; c < n_clouds; ++c) {
+    mls::CloudDev &cd = gh.clouds_host[c];
+    const int64_t cnt = gh.offsets[c + 1] - gh.offsets[c];
+    const int64_t fin = cnt - (int64_t)nonfin_h[c];
+    gh.finite_counts[c] = fin;
+    nonfinite_total += (int64_t)nonfin_h[c];
+    min_finite = std::min(min_finite, fin);
+    cd.begin = gh.offsets[c];
+    cd.end = gh.offsets[c + 1];
+    cd.sbegin = sorted_at;
+    cd.send = sorted_at + fin;
+    sorted_at += fin;
+    cd.h = h[c];
+    double lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
+    if (fin > 0)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = (double)ordered_to_float(bbox_h[6 * c + a]);
+        ext[a] = (double)ordered_to_float(bbox_h[6 * c + 3 + a]) - lo[a];
+      }
+    double cell = (cell_size && cell_size[c] > 0.0) ? cell_size[c] : 3.0 * h[c];
+    const double max_ext = std::max(ext[0], std::max(ext[1], ext[2]));
+    const double limit = (double)((1ll << max_bits) - 1);
+    if (max_ext / cell >= limit) cell = max_ext / (limit - 1.0);
+    cd.cell = cell;
+    cd.inv_cell = 1.0 / cell;
+    for (int a = 0; a < 3; ++a) {
+      cd.origin[a] = lo[a];
+      int64_t d = (int64_t)floor(ext[a] * cd.inv_cell) + 1;
+      if (d < 1) d = 1;
+      if (d > (1ll << max_bits)) d = 1ll << max_bits;
+      cd.dims[a] = (int32_t)d;
+      while ((1ll << bits) < d) ++bits;
+    }
+  }
+  for (int32_t c = 0; c < n_clouds; ++c) gh.clouds_host[c].bits = bits;
+  const int key_bits = 3 * bits + cloud_bits + 1;  // top bit separates non-finite keys
+
+  STEP(hipMemcpyAsync(clouds, gh.clouds_host, sizeof(mls::CloudDev) * (size_t)n_clouds,
+                      hipMemcpyHostToDevice, s));
+  STEP(mls::launch_keys(points, clouds, n_clouds, max_cloud, bits, keys_a, vals_a, s));
+  bool in_alt = false;
+  STEP(mls::radix_sort_pairs(keys_a, vals_a, keys_b, vals_b, n_points, key_bits, ws + L.radix,
+                             &in_alt, s));
+  const uint64_t *skeys = in_alt ? keys_b : keys_a;
+  const int32_t *svals = in_alt ? vals_b : vals_a;
+  STEP(mls::launch_gather(points, svals, n_points, pts, inv_perm, s));
+  STEP(hipMemsetAsync(counter, 0, 8, s));
+  STEP(mls::launch_count_cells(skeys, n_points, counter, s));
+  unsigned long long ncells = 0;
+  STEP(hipMemcpyAsync(&ncells, counter, 8, hipMemcpyDeviceToHost, s));
+  STEP(hipStreamSynchronize(s));
+  const uint64_t cap = next_pow2(std::max<uint64_t>(2 * (uint64_t)ncells, 64));
+  STEP(mls::launch_build_table(skeys, n_points, table, cap, s));
+#undef STEP
+
+  gh.view.pts = pts;
+  gh.view.inv_perm = inv_perm;
+  gh.view.table = table;
+  gh.view.clouds = clouds;
+  gh.view.hash_mask = cap - 1;
+  gh.view.n_clouds = n_clouds;
+  gh.view.morton_bits = bits;
+  gh.view.n_points = n_points;
+  gh.n_points = n_points;
+  gh.n_clouds = n_clouds;
+  gh.key_bits = key_bits;
+  gh.n_cells = (int64_t)ncells;
+  gh.hash_capacity = (int64_t)cap;
+  gh.n_nonfinite = nonfinite_total;
+  gh.min_cloud_finite = min_finite;
+  gh.clouds_dev = clouds;
+  gh.workspace = workspace;
+  gh.workspace_bytes = workspace_bytes;
+  *out_grid = G;
+  return cleanup(MLS_OK);
+}
+
+mls_status mls_grid_destroy(mls_grid *grid) {
+  if (!grid) return MLS_ERR_INVALID_ARGUMENT;
+  free(grid->g.offsets);
+  free(grid->g.finite_counts);
+  free(grid->g.clouds_host);
+  delete grid;
+  return MLS_OK;
+}
+
+mls_status mls_get_grid_info(const mls_grid *grid, mls_grid_info *info) {
+  if (!grid || !info) return MLS_ERR_INVALID_ARGUMENT;
+  const mls::GridHost &g = grid->g;
+  info->n_points = g.n_points;
+  info->n_clouds = g.n_clouds;
+  info->key_bits = g.key_bits;
+  info->n_cells = g.n_cells;
+  info->hash_capacity = g.hash_capacity;
+  info->n_nonfinite = g.n_nonfinite;
+  info->min_cloud_finite = g.min_cloud_finite;
+  return MLS_OK;
+}
+
+mls_status mls_get_cloud_grid(const mls_grid *grid, int32_t c, double origin[3], double *cell,
+                              int32_t dims[3]) {
+  if (!grid || !origin || !cell || !dims || c < 0 || c >= grid->g.n_clouds)
+    return MLS_ERR_INVALID_ARGUMENT;
+  const mls::CloudDev &cd = grid->g.clouds_host[c];
+  for (int a = 0; a < 3; ++a) {
+    origin[a] = cd.origin[a];
+    dims[a] = cd.dims[a];
+  }
+  *cell = cd.cell;
+  return MLS_OK;
+}
+
+mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
+                                  const int32_t **inverse_perm) {
+  if (!grid || !xyzw || !inverse_perm) return MLS_ERR_INVALID_ARGUMENT;
+  *xyzw = grid->g.view.pts;
+  *inverse_perm = grid->g.view.inv_perm;
+  return MLS_OK;
+}
+
+size_t mls_project_workspace_bytes(const mls_grid *grid, int32_t k, int64_t n_queries) {
+  if (!grid || k < 1 || k > MLS_MAX_K || n_queries < 0) return 0;
+  return proj_layout(grid->g.n_clouds, k, n_queries).total;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared validation and set-up of mls_knn / mls_project / mls_project_backward.
+mls_status prepare_queries(const mls_grid *grid, int32_t k, const void *queries, mls_dtype dtype,
+                           int64_t n, const int64_t *query_offsets, void *workspace,
+                           size_t workspace_bytes, hipStream_t s, mls::QueryView *qv,
+                           ProjLayout *L) {
+  if (!grid || k < 1 || k > MLS_MAX_K || n < 0 || n > 0x7fffffffll) return MLS_ERR_INVALID_ARGUMENT;
+  if (dtype != MLS_F32 && dtype != MLS_F64) return MLS_ERR_INVALID_ARGUMENT;
+  if (n > 0 && (!queries || !workspace)) return MLS_ERR_INVALID_ARGUMENT;
+  const mls::GridHost &g = grid->g;
+  if (k > g.min_cloud_finite) return MLS_ERR_TOO_FEW_POINTS;
+  const int32_t C = g.n_clouds;
+  const bool aligned = !query_offsets && n == g.n_points;
+  if (query_offsets) {
+    if (!offsets_ok(query_offsets, C, n)) return MLS_ERR_INVALID_ARGUMENT;
+  } else if (C > 1 && !aligned) {
+    return MLS_ERR_INVALID_ARGUMENT;
+  }
+  *L = proj_layout(C, k, n);
+  if (n > 0 && ((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
+  if (n > 0 && workspace_bytes < L->total) return MLS_ERR_WORKSPACE_TOO_SMALL;
+  mls_status st = check_async();
+  if (st != MLS_OK) return st;
+  char *ws = (char *)workspace;
+  qv->q = queries;
+  qv->is_f64 = dtype == MLS_F64;
+  qv->n = n;
+  qv->order = nullptr;
+  qv->aligned = aligned ? 1 : 0;
+  qv->qcloud = nullptr;
+  if (C > 1 && n > 0) {
+    int64_t *off_dev = (int64_t *)(ws + L->offsets);
+    int32_t *qcloud = (int32_t *)(ws + L->qcloud);
+    const int64_t *src = query_offsets ? query_offsets : g.offsets;
+    MLS_HIP(hipMemcpyAsync(off_dev, src, 8 * ((size_t)C + 1), hipMemcpyHostToDevice, s));
+    MLS_HIP(mls::launch_fill_cloud_ids(off_dev, C, n, qcloud, s));
+    qv->qcloud = qcloud;
+  }
+  return MLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries, mls_dtype dtype,
+                   int64_t n_queries, const int64_t *query_offsets, int32_t *out_neighbors,
+                   double *out_keys, void *workspace, size_t workspace_bytes, void *stream) {
+  g_last_error[0] = 0;
+  if (n_queries > 0 && !out_neighbors) return MLS_ERR_INVALID_ARGUMENT;
+  hipStream_t s = (hipStream_t)stream;
+  mls::QueryView qv;
+  ProjLayout L;
+  mls_status st = prepare_queries(grid, k, queries, dtype, n_queries, query_offsets, workspace,
+                                  workspace_bytes, s, &qv, &L);
+  if (st != MLS_OK || n_queries == 0) return st;
+  char *ws = (char *)workspace;
+  MLS_HIP(mls::launch_knn(grid->g.view, qv, k, 3.0, (int32_t *)(ws + L.nbr),
+                          (uint8_t *)(ws + L.support), out_neighbors, out_keys, s));
+  return MLS_OK;
+}
+
+mls_status mls_project(const mls_grid *grid, const mls_params *params, const void *queries,
+                       mls_dtype dtype, int64_t n_queries, const int64_t *query_offsets,
+                       void *out_points, uint8_t *out_status, int32_t *out_neighbors,
+                       void *workspace, size_t workspace_bytes, void *stream) {
+  g_last_error[0] = 0;
+  if (!params) return MLS_ERR_INVALID_ARGUMENT;
+  if (params->precision != MLS_PREC_FP64 && params->precision != MLS_PREC_FP32_MOMENTS)
+    return MLS_ERR_INVALID_ARGUMENT;
+  if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
+      params->min_support < 0 || params->reserved != 0)
+    return MLS_ERR_INVALID_ARGUMENT;
+  if (n_queries > 0 && (!out_points || !out_status)) return MLS_ERR_INVALID_ARGUMENT;
+  hipStream_t s = (hipStream_t)stream;
+  mls::QueryView qv;
+  ProjLayout L;
+  mls_status st = prepare_queries(grid, params->k, queries, dtype, n_queries, query_offsets,
+                                  workspace, workspace_bytes, s, &qv, &L);
+  if (st != MLS_OK || n_queries == 0) return st;
+  char *ws = (char *)workspace;
+  int32_t *nbr = (int32_t *)(ws + L.nbr);
+  uint8_t *support = (uint8_t *)(ws + L.support);
+  MLS_HIP(mls::launch_knn(grid->g.view, qv, params->k, params->support_radius_h, nbr, support,
+                          out_neighbors, nullptr, s));
+  MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
+                                  params->min_support, nbr, support, out_points, out_status, s));
+  return MLS_OK;
+}
+
+mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
+                                const void *queries, mls_dtype dtype, int64_t n_queries,
+                                const int64_t *query_offsets, const int32_t *neighbors,
+                                const void *grad_out, void *grad_queries, void *grad_points,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+  (void)queries; (void)dtype; (void)n_queries; (void)query_offsets;
+  (void)neighbors; (void)grad_out; (void)grad_queries; (void)grad_points; (void)workspace;
+  (void)workspace_bytes; (void)stream;
+  if (!grid || !params) return MLS_ERR_INVALID_ARGUMENT;
+  return MLS_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

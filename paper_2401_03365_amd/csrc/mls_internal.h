@@ -1,0 +1,150 @@
+// mls_internal.h -- types and small device helpers shared by the kernels of
+// libmls.so (grid build, neighbour search, forward and adjoint projection).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mls.h"
+
+namespace mls {
+
+constexpr int kWave = 64;
+constexpr uint64_t kEmptyKey = ~0ull;  // hash slot marker and non-finite point key
+
+// Per-cloud geometry and parameters, resident in device memory.
+struct CloudDev {
+  double origin[3];  // grid origin (minimum corner of the cloud's box)
+  double cell;       // cell edge
+  double inv_cell;   // 1 / cell
+  double h;          // Gaussian width
+  int32_t dims[3];   // cells per axis
+  int32_t bits;      // Morton bits per axis used by the key
+  int64_t begin;     // first original point index of the cloud
+  int64_t end;       // one past the last
+  int64_t sbegin;    // sorted positions [sbegin, send) hold the cloud's finite points
+  int64_t send;
+};
+
+// Device-resident view of a built grid, passed to kernels by value.
+struct GridView {
+  const float4 *pts;         // sorted points, w = original index bits
+  const int32_t *inv_perm;   // original index -> sorted position
+  const uint4 *table;        // hash slots: {key lo, key hi, start, count}
+  const CloudDev *clouds;    // n_clouds entries
+  uint64_t hash_mask;        // capacity - 1
+  int32_t n_clouds;
+  int32_t morton_bits;       // bits per axis in the key (same for all clouds)
+  int64_t n_points;
+};
+
+// Host-side handle contents.
+struct GridHost {
+  GridView view;
+  int64_t n_points;
+  int32_t n_clouds;
+  int32_t key_bits;
+  int64_t n_cells;
+  int64_t hash_capacity;
+  int64_t n_nonfinite;
+  int64_t min_cloud_finite;
+  int64_t *offsets;          // host copy, n_clouds + 1
+  int64_t *finite_counts;    // host, n_clouds
+  CloudDev *clouds_host;     // host copy of the device table
+  CloudDev *clouds_dev;      // in the workspace
+  void *workspace;
+  size_t workspace_bytes;
+};
+
+// ---- small device helpers -------------------------------------------------
+
+__device__ __forceinline__ uint64_t spread_bits3(uint32_t v) {
+  // spread the low 21 bits of v to every third bit
+  uint64_t x = v & 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t cell_key(int32_t cloud, int32_t ix, int32_t iy,
+                                             int32_t iz, int32_t bits) {
+  uint64_t m = spread_bits3((uint32_t)ix) | (spread_bits3((uint32_t)iy) << 1) |
+               (spread_bits3((uint32_t)iz) << 2);
+  return ((uint64_t)cloud << (3 * bits)) | m;
+}
+
+__device__ __forceinline__ uint64_t hash64(uint64_t x) {
+  // splitmix64 finaliser
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+// Returns {start, count} of the cell, count 0 if the cell is empty.
+__device__ __forceinline__ int2 lookup_cell(const GridView &g, uint64_t key) {
+  uint64_t slot = hash64(key) & g.hash_mask;
+  for (uint64_t probe = 0; probe <= g.hash_mask; ++probe) {
+    uint4 e = g.table[slot];
+    uint64_t k = (uint64_t)e.x | ((uint64_t)e.y << 32);
+    if (k == key) {
+      // a cell range always lies inside the sorted array
+      const int64_t st = (int64_t)e.z, ct = (int64_t)e.w;
+      if (st + ct > g.n_points) return make_int2(0, 0);
+      return make_int2((int)st, (int)ct);
+    }
+    if (k == kEmptyKey) return make_int2(0, 0);
+    slot = (slot + 1) & g.hash_mask;
+  }
+  return make_int2(0, 0);
+}
+
+// Cell coordinate of a coordinate along one axis (no clamping).
+__device__ __forceinline__ int64_t cell_coord(double x, double origin, double inv_cell) {
+  return (int64_t)floor((x - origin) * inv_cell);
+}
+
+}  // namespace mls
+
+// ---- host launchers (defined in the .hip files) -----------------------------
+namespace mls {
+hipError_t launch_bbox(const float *pts, const int64_t *offsets_dev, int32_t n_clouds,
+                       int64_t max_cloud, uint32_t *bbox_bits, unsigned long long *nonfinite,
+                       hipStream_t s);
+hipError_t launch_keys(const float *pts, const CloudDev *clouds, int32_t n_clouds,
+                       int64_t max_cloud, int32_t bits, uint64_t *keys, int32_t *vals,
+                       hipStream_t s);
+size_t radix_temp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
+                            int64_t n, int32_t key_bits, void *temp, bool *result_in_alt,
+                            hipStream_t s);
+hipError_t launch_gather(const float *pts, const int32_t *vals, int64_t n, float4 *sorted,
+                         int32_t *inv_perm, hipStream_t s);
+hipError_t launch_count_cells(const uint64_t *keys, int64_t n, unsigned long long *count,
+                              hipStream_t s);
+hipError_t launch_build_table(const uint64_t *keys, int64_t n, uint4 *table, uint64_t capacity,
+                              hipStream_t s);
+
+struct QueryView {
+  const void *q;            // queries, n x 3
+  int32_t is_f64;
+  int64_t n;
+  const int32_t *order;     // processing order -> query index, or null (identity)
+  const int32_t *qcloud;    // per query cloud id, or null (cloud 0)
+  int32_t aligned;          // queries aligned with points: order from the grid
+};
+
+hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, double support_r_h,
+                      int32_t *nbr_tiles, uint8_t *support, int32_t *out_nbr, double *out_keys,
+                      hipStream_t s);
+hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
+                              int32_t precision, int32_t min_support, const int32_t *nbr_tiles,
+                              const uint8_t *support, void *out, uint8_t *status, hipStream_t s);
+hipError_t launch_fill_cloud_ids(const int64_t *offsets_dev, int32_t n_clouds, int64_t n,
+                                 int32_t *qcloud, hipStream_t s);
+}  // namespace mls

@@ -1,0 +1,116 @@
+"""GPU parity of the exact k-nearest-neighbour search: lists and FP64 keys
+must equal the oracle's brute force bit for bit (ties to the smaller index)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_03365_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def api():
+    from paper_2401_03365_amd import api as a
+    return a
+
+
+def run_knn(P32, Q, k, h, cell_size=None, offsets=None, qoffsets=None):
+    a = api()
+    Pt = torch.from_numpy(np.ascontiguousarray(P32, dtype=np.float32)).cuda()
+    Qt = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    g = a.Grid(Pt, h, cloud_offsets=offsets, cell_size=cell_size)
+    nbr, keys = g.knn(Qt, k, query_offsets=qoffsets, return_keys=True)
+    torch.cuda.synchronize()
+    return nbr.cpu().numpy(), keys.cpu().numpy(), g
+
+
+def assert_lists_equal(orc, P32, Q, k, nbr, keys):
+    ref_idx, ref_key = orc.knn(P32.astype(np.float64), np.asarray(Q, dtype=np.float64), k)
+    bad = np.nonzero((nbr != ref_idx).any(axis=1))[0]
+    assert bad.size == 0, "first mismatching queries %s: gpu %s oracle %s" % (
+        bad[:3], nbr[bad[:1]], ref_idx[bad[:1]])
+    assert np.array_equal(keys.view(np.uint64), ref_key.view(np.uint64)) or \
+        np.array_equal(np.nan_to_num(keys, nan=-1), np.nan_to_num(ref_key, nan=-1))
+
+
+def test_sphere_c1_bit_exact(orc):
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    nbr, keys, g = run_knn(P, P, 32, h)
+    assert_lists_equal(orc, P, P, 32, nbr, keys)
+    assert g.info()["n_nonfinite"] == 0
+
+
+ADVERSARIAL = {
+    "lattice3d": (lambda: synth.lattice(9, 8, 7, spacing=0.25), 0.25),
+    "duplicates": (lambda: np.repeat(synth.sphere(300, 0.0, seed=8), 5, axis=0), 0.05),
+    "collinear": (lambda: synth.lattice(200, 1, 1, spacing=0.5), 0.5),
+    "planar_lattice": (lambda: synth.lattice(40, 40, 1, spacing=1.0), 1.0),
+    "n_equals_k": (lambda: synth.sphere(32, 0.1, seed=3), 0.3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("cell_factor", [0.3, 1.0, 3.0, 40.0])
+def test_adversarial_clouds(orc, name, cell_factor):
+    make, h = ADVERSARIAL[name]
+    P = make()
+    k = min(32, P.shape[0])
+    nbr, keys, _ = run_knn(P, P, k, h, cell_size=cell_factor * h)
+    assert_lists_equal(orc, P, P, k, nbr, keys)
+
+
+def test_off_cloud_and_far_queries(orc):
+    P = synth.torus(5000, sigma=0.005, seed=2)
+    h = synth.mean_nn_h(P)
+    rng = np.random.default_rng(5)
+    Q = np.vstack([rng.uniform(-1.5, 1.5, (400, 3)),          # in and around the box
+                   rng.uniform(-40, 40, (40, 3)),              # far outside: exhaustive path
+                   P[:200] + rng.normal(0, 3 * h, (200, 3))]).astype(np.float32)
+    nbr, keys, _ = run_knn(P, Q, 24, h)
+    assert_lists_equal(orc, P, Q, 24, nbr, keys)
+
+
+def test_fp64_queries(orc):
+    P = synth.sphere(3000, 0.02, seed=4)
+    h = synth.mean_nn_h(P)
+    rng = np.random.default_rng(6)
+    Q = P.astype(np.float64) + rng.normal(0, 1e-3, (3000, 3))
+    nbr, keys, _ = run_knn(P, Q, 16, h)
+    assert_lists_equal(orc, P, Q, 16, nbr, keys)
+
+
+def test_nonfinite_points_and_queries(orc):
+    P = synth.sphere(2000, 0.01, seed=9)
+    P[[5, 77, 1999]] = np.nan
+    P[100, 1] = np.inf
+    h = 0.08
+    Q = P.copy()
+    nbr, keys, g = run_knn(P, Q, 12, h)
+    assert g.info()["n_nonfinite"] == 4
+    assert_lists_equal(orc, P, Q, 12, nbr, keys)
+    assert np.all(nbr[[5, 77, 100, 1999]] == -1)
+
+
+def test_batch_of_clouds_lists_per_cloud(orc):
+    parts = [synth.sphere(1500, 0.01, seed=11), synth.torus(2500, sigma=0.01, seed=12),
+             synth.heightfield(3000, sigma=1e-3, seed=13)]
+    sizes = [p.shape[0] for p in parts]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    P = np.concatenate(parts)
+    hs = [synth.mean_nn_h(p) for p in parts]
+    nbr, keys, g = run_knn(P, P, 20, hs, offsets=offs)
+    for c, p in enumerate(parts):
+        sl = slice(offs[c], offs[c + 1])
+        ref_idx, ref_key = orc.knn(p.astype(np.float64), p.astype(np.float64), 20)
+        np.testing.assert_array_equal(nbr[sl] - offs[c], ref_idx)
+        np.testing.assert_array_equal(keys[sl], ref_key)
+
+
+def test_determinism():
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    a, ka, _ = run_knn(P, P, 32, h)
+    b, kb, _ = run_knn(P, P, 32, h, cell_size=2.0 * h)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(ka, kb)

@@ -1,0 +1,143 @@
+"""GPU parity of the forward MLS projection against the FP64 oracle.
+
+Tolerances (in units of h, on points whose normal is not flagged ambiguous):
+FP64 path max |out - oracle| <= 1e-10 h; FP32-moment path RMS <= 1e-5 h.
+Statuses (low nibble) must match exactly."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_03365_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_MAX_H = 1e-10
+FP32_RMS_H = 1e-5
+
+
+def api():
+    from paper_2401_03365_amd import api as a
+    return a
+
+
+def gpu_project(P32, Q, k, h, precision, cell_size=None, return_neighbors=False):
+    a = api()
+    Pt = torch.from_numpy(np.ascontiguousarray(P32, dtype=np.float32)).cuda()
+    Qt = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    g = a.Grid(Pt, h, cell_size=cell_size)
+    res = g.project(Qt, k, precision, return_neighbors=return_neighbors)
+    torch.cuda.synchronize()
+    return tuple(r.cpu().numpy() for r in res)
+
+
+def compare(orc, P32, Q, k, h, out, st, precision):
+    """Outputs carry the query dtype; with FP32 outputs the storage rounding
+    (half an FP32 ulp per coordinate) is added to the tolerance."""
+    ref, ref_st = orc.project(P32.astype(np.float64), np.asarray(Q, dtype=np.float64), k, h)
+    np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    diff = np.abs(out.astype(np.float64) - ref)
+    if out.dtype == np.float32:
+        diff = np.maximum(diff - np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
+    err = np.linalg.norm(diff, axis=1)[ok] / h
+    if precision == "fp64":
+        assert err.max() <= FP64_MAX_H, err.max()
+    else:
+        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
+    return err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("io", ["f64", "f32"])
+def test_sphere_c1(orc, precision, io):
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    Q = P.astype(np.float64) if io == "f64" else P
+    out, st = gpu_project(P, Q, 32, h, precision)
+    assert out.dtype == Q.dtype
+    compare(orc, P, Q, 32, h, out, st, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_torus_with_outliers(orc, precision):
+    P = synth.torus(50000, sigma=0.005, n_outliers=500, seed=2)
+    h = synth.mean_nn_h(P)
+    out, st = gpu_project(P, P.astype(np.float64), 32, h, precision)
+    compare(orc, P, P, 32, h, out, st, precision)
+    assert ((st & 0x0F) == 1).sum() > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_heightfield_k48(orc, precision):
+    P = synth.heightfield(30000, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    out, st = gpu_project(P, P.astype(np.float64), 48, h, precision)
+    compare(orc, P, P, 48, h, out, st, precision)
+
+
+def test_plane_and_quadric_closed_forms():
+    from tests.test_oracle_project import load_golden, plane_case, quadric_case
+    gold = load_golden()
+    for c in gold["planes"]:
+        P, Q, feet, n = plane_case(c)
+        out, st = gpu_project(P.astype(np.float32), Q, c["k"], c["h"], "fp64")
+        assert np.all((st & 0x0F) == 0)
+        assert np.abs(out - feet).max() < 1e-12
+    for c in gold["quadric_apex"]:
+        P, Q = quadric_case(c)
+        out, st = gpu_project(P.astype(np.float32), Q, P.shape[0], c["h"], "fp64")
+        assert (st[0] & 0x0F) == 0
+        np.testing.assert_allclose(out[0], c["expected"], rtol=0, atol=1e-13)
+
+
+def test_iterated_passes_match_oracle_per_pass(orc):
+    P = synth.heightfield(20000, sigma=1e-3, seed=33)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    cur = Pt.double()
+    for it in range(3):
+        out, st = g.project(cur, 48, "fp32")
+        q = cur.cpu().numpy()
+        ref, ref_st = orc.project(P.astype(np.float64), q.astype(np.float64), 48, h)
+        stn = st.cpu().numpy()
+        np.testing.assert_array_equal(stn & 0x0F, ref_st & 0x0F)
+        ok = (ref_st & 0x10) == 0
+        err = np.linalg.norm(out.cpu().numpy().astype(np.float64) - ref, axis=1)[ok] / h
+        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+        cur = out
+
+
+def test_in_place_output_and_empty_input():
+    P = synth.sphere(4000, 0.01, seed=5)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    ref, _ = g.project(Pt.clone(), 16, "fp64")
+    q = Pt.clone()
+    g.project(q, 16, "fp64", out=q)
+    torch.cuda.synchronize()
+    assert torch.equal(q, ref)
+    e = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    out, st = g.project(e, 16, "fp64")
+    assert out.shape == (0, 3) and st.shape == (0,)
+
+
+def test_statuses_on_gpu(orc):
+    P = np.vstack([synth.lattice(6, 6, 1, spacing=0.1), [[5.0, 5.0, 5.0]]]).astype(np.float32)
+    out, st = gpu_project(P, P, 8, 0.1, "fp64")
+    assert (st[-1] & 0x0F) == 1
+    np.testing.assert_array_equal(out[-1], P[-1])
+    L = synth.lattice(40, 1, 1, spacing=0.05)
+    out, st = gpu_project(L, L[10:30], 12, 0.1, "fp64")
+    assert np.all((st & 0x0F) == 2)
+    ref, ref_st = orc.project(L.astype(np.float64), L[10:30].astype(np.float64), 12, 0.1)
+    np.testing.assert_allclose(out, ref, atol=1e-12)
+    Q = np.array([[np.nan, 0, 0], [0.1, 0.1, np.inf]], dtype=np.float32)
+    out, st = gpu_project(P, Q, 8, 0.1, "fp64")
+    assert np.all(st == 3) and np.all(np.isnan(out))
