@@ -1,0 +1,246 @@
+"""Benchmark of the MLS projection hot path on one MI355X.
+
+Workload (the metric's configuration): a 10,000,000-point noisy height field
+(8 random sinusoids of amplitude 0.05 and frequency 1..8 over [0,1]^2,
+sampling density ramping 10x across x, noise sigma 1e-3 along the normal),
+k = 48, three iterated projection passes with the FP32-moment path.
+
+One step = build the grid of the cloud + 3 passes (each pass: exact kNN
+search, then moments / plane / quadratic fit / projection), inputs resident
+in HBM. value = 3 N / step time. The same steps are also timed with the FP64
+path. Kernel durations come from HIP events recorded on the stream the
+library launches on; the CPU oracle is timed on a bounded sample of the same
+workload.
+
+Prints one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLS projected points/sec @10M pts k=48: FP32 vs FP64 path; fwd+bwd pts/sec"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+# Algorithmic work per query of the fit kernel (moments, plane, quadratic fit,
+# projection): FP32 operations per neighbour (pass 1: 34, pass 2: 74; an
+# exponential counted as one operation each pass) plus the FP64 per-point
+# algebra (eigen-solve, frame, 6x6 Cholesky and solve: ~1,000 operations).
+FIT_FLOPS_PER_NEIGHBOUR = 108 + 2
+FIT_FP64_FLOPS_PER_QUERY = 1000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--k", type=int, default=48)
+    ap.add_argument("--passes", type=int, default=3)
+    ap.add_argument("--cell-factor", type=float, default=None,
+                    help="cell edge in units of h (default: library tuning table)")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    return ap.parse_args()
+
+
+def default_cell_factor(k):
+    # edge of the finest grid level in units of h (the search picks coarser
+    # levels where the density needs them)
+    return 1.25
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+        self.acc = {}
+
+    def span(self, name):
+        torch = self.torch
+        timer = self
+
+        class _S:
+            def __enter__(self):
+                self.a = torch.cuda.Event(enable_timing=True)
+                self.b = torch.cuda.Event(enable_timing=True)
+                self.a.record()
+
+            def __exit__(self, *exc):
+                self.b.record()
+                timer.acc.setdefault(name, []).append((self.a, self.b))
+        return _S()
+
+    def ms(self, name):
+        ev = self.acc.get(name, [])
+        return sum(a.elapsed_time(b) for a, b in ev) / max(1, len(ev))
+
+    def reset(self):
+        self.acc = {}
+
+
+def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer):
+    """Returns (ms_per_step, last outputs of pass 1, last final outputs)."""
+    q0 = pts.double()
+    first = None
+    out = None
+
+    def step(record):
+        nonlocal first, out
+        ctx = timer.span if record else (lambda name: _Null())
+        with ctx("build"):
+            grid = api.Grid(pts, h, cell_size=cell)
+        cur = q0
+        status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
+        for p in range(passes):
+            nxt = torch.empty_like(cur)
+            with ctx("search"):
+                grid.project(cur, k, precision, stages=1, out=nxt, status=status)
+            with ctx("fit"):
+                grid.project(cur, k, precision, stages=2, out=nxt, status=status)
+            if p == 0:
+                first = nxt
+            cur = nxt
+        out = cur
+        return grid
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    timer.reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1000.0 / steps, first, out
+
+
+class _Null:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2401_03365_amd import api, synth
+
+    t = time.perf_counter()
+    P = synth.heightfield(args.n, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    log("cloud %d pts generated, h = %.6g (%.1f s)" % (args.n, h, time.perf_counter() - t))
+    cf = args.cell_factor if args.cell_factor is not None else default_cell_factor(args.k)
+    cell = cf * h
+    pts = torch.from_numpy(P).cuda()
+    torch.cuda.synchronize()
+
+    timer = Timer(torch)
+    ms32, first32, out32 = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", cell,
+                                     args.steps, args.warmup, timer)
+    br32 = {n: timer.ms(n) for n in ("build", "search", "fit")}
+    log("fp32: %.2f ms/step  build %.2f  search %.2f  fit %.2f (ms per call)" %
+        (ms32, br32["build"], br32["search"], br32["fit"]))
+    value = args.n * args.passes / (ms32 / 1000.0)
+
+    fp64 = None
+    first64 = None
+    if not args.no_fp64:
+        timer64 = Timer(torch)
+        ms64, first64, _ = run_steps(api, torch, pts, h, args.k, args.passes, "fp64", cell,
+                                     max(1, args.steps // 2), 1, timer64)
+        br64 = {n: timer64.ms(n) for n in ("build", "search", "fit")}
+        log("fp64: %.2f ms/step  build %.2f  search %.2f  fit %.2f" %
+            (ms64, br64["build"], br64["search"], br64["fit"]))
+        fp64 = {"value": args.n * args.passes / (ms64 / 1000.0), "unit": "pts/s",
+                "ms_per_step": ms64, "breakdown_ms": br64}
+
+    # roofline of the dominant kernel
+    nq = args.n
+    if br32["fit"] >= br32["search"]:
+        flops = nq * (args.k * FIT_FLOPS_PER_NEIGHBOUR + FIT_FP64_FLOPS_PER_QUERY)
+        achieved = flops / (br32["fit"] / 1000.0) / 1e12
+        roof = {"kernel": "mls_fit_fp32", "bound": "alu", "achieved": achieved,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": None}
+    else:
+        # neighbour search: algorithmic bytes per query = query (24) + sorted
+        # cloud read once (16) + list out (4 k) + support (1)
+        byt = nq * (24 + 16 + 4 * args.k + 1)
+        achieved = byt / (br32["search"] / 1000.0) / 1e9
+        roof = {"kernel": "knn_search", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None}
+
+    res = {"metric": METRIC, "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "heightfield-10M-k48-3pass", "n_points": args.n, "k": args.k,
+                      "passes": args.passes, "precision": "fp32-moments+fp64-solves",
+                      "h": h, "cell_size": cell, "step": "grid build + %d passes" % args.passes},
+           "breakdown_ms": br32,
+           "value_excl_build": args.n * args.passes /
+           ((ms32 - br32["build"]) / 1000.0),
+           "fp64_path": fp64,
+           "roofline": roof}
+
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(7)
+        sample = np.sort(rng.choice(args.n, size=min(args.cpu_sample, args.n), replace=False))
+        P64 = P.astype(np.float64)
+        Q = P64[sample]
+        t = time.perf_counter()
+        nbr, _ = oracle.knn(P64, Q, args.k)
+        ref, ref_st = oracle.project(P64, Q, args.k, h, nbr=nbr)
+        dt = time.perf_counter() - t
+        t2 = time.perf_counter()
+        oracle.project(P64, Q, args.k, h, nbr=nbr)
+        dt_fit = time.perf_counter() - t2
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": len(sample) / dt, "unit": "pts/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "%d random queries of pass 1 of the same 10M cloud "
+                                         "(brute-force kNN over all points + FP64 projection)"
+                                         % len(sample),
+                               "fit_only_pts_s": len(sample) / dt_fit}
+        ok = (ref_st & 0x10) == 0
+        acc = {}
+        for name, first in (("fp32", first32), ("fp64", first64)):
+            if first is None:
+                continue
+            g = first.cpu().numpy()[sample]
+            e = np.linalg.norm(g - ref, axis=1)[ok] / h
+            acc[name] = {"rms_over_h": float(np.sqrt((e ** 2).mean())), "max_over_h": float(e.max()),
+                         "n": int(ok.sum())}
+        res["accuracy_pass1_vs_oracle"] = acc
+        log("cpu oracle %.0f pts/s on %d cores; accuracy %s" % (len(sample) / dt, cores, acc))
+
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -90,8 +90,18 @@ typedef struct {
   int32_t precision;        /* mls_precision */
   double support_radius_h;  /* outlier radius in units of h (default 3.0) */
   int32_t min_support;      /* outlier threshold (default 3) */
-  int32_t reserved;         /* must be 0 */
+  int32_t stages;           /* mls_stage bits; 0 = MLS_STAGE_ALL */
 } mls_params;
+
+/* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and
+ * support counts in the workspace; a later call with MLS_STAGE_FIT on the
+ * same grid, queries, k, query_offsets and workspace (stream-ordered after
+ * it) fits and projects from them, so one search can serve several fits. */
+typedef enum {
+  MLS_STAGE_ALL = 0,
+  MLS_STAGE_SEARCH = 1,
+  MLS_STAGE_FIT = 2
+} mls_stage;
 
 /* Library version string (host). */
 const char *mls_version(void);
@@ -119,9 +129,11 @@ size_t mls_grid_workspace_bytes(int64_t n_points, int32_t n_clouds);
  *   cloud_offsets   (host) n_clouds+1 ascending offsets into points, first 0,
  *                   last n_points; NULL means one cloud.
  *   h               (host) n_clouds Gaussian widths, finite and > 0.
- *   cell_size       (host) n_clouds cell edges, or NULL; entries <= 0 select
- *                   3h. The edge grows when a cloud would need more than
- *                   2^21 cells along an axis.
+ *   cell_size       (host) n_clouds edges of the finest cells, or NULL;
+ *                   entries <= 0 select 1.25 h. The grid also indexes cells
+ *                   of 2, 4, ..., 128 times that edge (each a contiguous
+ *                   Morton range of the sorted points). The edge grows when
+ *                   a cloud would need more than 2^19 cells along an axis.
  *   workspace       device buffer of at least mls_grid_workspace_bytes(),
  *                   256-byte aligned; it holds the grid and must outlive it.
  *   out_grid        (host) receives the handle.

@@ -134,23 +134,27 @@ class Grid:
         _abi.check(code, "mls_knn")
         return (nbr, keys) if return_keys else nbr
 
-    def _params(self, k, precision, support_radius_h, min_support):
+    def _params(self, k, precision, support_radius_h, min_support, stages=0):
         if precision not in PRECISIONS:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
                               support_radius_h=float(support_radius_h),
-                              min_support=int(min_support), reserved=0)
+                              min_support=int(min_support), stages=int(stages))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
-                support_radius_h: float = 3.0, min_support: int = 3):
-        """One MLS projection pass. Returns (out, status[, neighbours])."""
+                support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
+                status: Optional[torch.Tensor] = None):
+        """One MLS projection pass. Returns (out, status[, neighbours]).
+        ``stages``: 0 = search and fit, 1 = search only (lists stay in the
+        grid's workspace), 2 = fit only from the preceding search."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
-        params = self._params(k, precision, support_radius_h, min_support)
+        params = self._params(k, precision, support_radius_h, min_support, stages)
         if out is None:
             out = torch.empty_like(queries)
-        status = torch.empty((n,), dtype=torch.uint8, device=self.device)
+        if status is None:
+            status = torch.empty((n,), dtype=torch.uint8, device=self.device)
         nbr = torch.empty((n, k), dtype=torch.int32, device=self.device) if return_neighbors else None
         ws = self._proj_workspace(k, n)
         qo, qo_p = _host_i64(query_offsets)

@@ -51,7 +51,7 @@ GridLayout grid_layout(int64_t n, int32_t c) {
   L.vals_a = take(4 * (size_t)n);
   L.vals_b = take(4 * (size_t)n);
   L.radix = take(mls::radix_temp_bytes(n));
-  L.table_cap_max = next_pow2(std::max<uint64_t>(2 * (uint64_t)n, 64));
+  L.table_cap_max = next_pow2(std::max<uint64_t>(4 * (uint64_t)n, 64));
   L.table = take(16 * L.table_cap_max);
   L.clouds = take(sizeof(mls::CloudDev) * (size_t)c);
   L.offsets = take(8 * ((size_t)c + 1));
@@ -208,7 +208,8 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   // per-cloud geometry: origin at the box minimum, dims covering the box
   int cloud_bits = 0;
   while ((1ll << cloud_bits) < n_clouds) ++cloud_bits;
-  const int max_bits = std::min(21, (63 - cloud_bits) / 3);
+  // the level tag of the cell hash sits in bits 60..62 of the key
+  const int max_bits = std::min(19, (59 - cloud_bits) / 3);
   int bits = 1;
   int64_t sorted_at = 0, nonfinite_total = 0, min_finite = INT64_MAX;
   for (int32_t c = 0; c < n_clouds; ++c) {
@@ -230,7 +231,7 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
         lo[a] = (double)ordered_to_float(bbox_h[6 * c + a]);
         ext[a] = (double)ordered_to_float(bbox_h[6 * c + 3 + a]) - lo[a];
       }
-    double cell = (cell_size && cell_size[c] > 0.0) ? cell_size[c] : 3.0 * h[c];
+    double cell = (cell_size && cell_size[c] > 0.0) ? cell_size[c] : 1.25 * h[c];
     const double max_ext = std::max(ext[0], std::max(ext[1], ext[2]));
     const double limit = (double)((1ll << max_bits) - 1);
     if (max_ext / cell >= limit) cell = max_ext / (limit - 1.0);
@@ -257,13 +258,23 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   const uint64_t *skeys = in_alt ? keys_b : keys_a;
   const int32_t *svals = in_alt ? vals_b : vals_a;
   STEP(mls::launch_gather(points, svals, n_points, pts, inv_perm, s));
-  STEP(hipMemsetAsync(counter, 0, 8, s));
-  STEP(mls::launch_count_cells(skeys, n_points, counter, s));
-  unsigned long long ncells = 0;
-  STEP(hipMemcpyAsync(&ncells, counter, 8, hipMemcpyDeviceToHost, s));
+  STEP(hipMemsetAsync(counter, 0, 8 * mls::kMaxLevels, s));
+  STEP(mls::launch_count_cells(skeys, n_points, mls::kMaxLevels, counter, s));
+  unsigned long long level_cells[mls::kMaxLevels] = {};
+  STEP(hipMemcpyAsync(level_cells, counter, 8 * mls::kMaxLevels, hipMemcpyDeviceToHost, s));
   STEP(hipStreamSynchronize(s));
-  const uint64_t cap = next_pow2(std::max<uint64_t>(2 * (uint64_t)ncells, 64));
-  STEP(mls::launch_build_table(skeys, n_points, table, cap, s));
+  // every level shares one hash; drop coarse levels if they would not fit
+  int n_levels = mls::kMaxLevels;
+  while (bits - (n_levels - 1) < 1) --n_levels;
+  uint64_t cap = 0;
+  for (;; --n_levels) {
+    uint64_t total = 0;
+    for (int l = 0; l < n_levels; ++l) total += level_cells[l];
+    cap = next_pow2(std::max<uint64_t>(2 * total, 64));
+    if (cap <= L.table_cap_max || n_levels == 1) break;
+  }
+  const unsigned long long ncells = level_cells[0];
+  STEP(mls::launch_build_table(skeys, n_points, n_levels, table, cap, s));
 #undef STEP
 
   gh.view.pts = pts;
@@ -274,6 +285,12 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   gh.view.n_clouds = n_clouds;
   gh.view.morton_bits = bits;
   gh.view.n_points = n_points;
+  gh.view.n_levels = n_levels;
+  {
+    int shift = 64;
+    for (uint64_t c = cap; c > 1; c >>= 1) --shift;
+    gh.view.hash_shift = shift;
+  }
   gh.n_points = n_points;
   gh.n_clouds = n_clouds;
   gh.key_bits = key_bits;
@@ -410,8 +427,9 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params, const voi
   if (params->precision != MLS_PREC_FP64 && params->precision != MLS_PREC_FP32_MOMENTS)
     return MLS_ERR_INVALID_ARGUMENT;
   if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
-      params->min_support < 0 || params->reserved != 0)
+      params->min_support < 0 || params->stages < 0 || params->stages > 3)
     return MLS_ERR_INVALID_ARGUMENT;
+  const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
   if (n_queries > 0 && (!out_points || !out_status)) return MLS_ERR_INVALID_ARGUMENT;
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
@@ -422,10 +440,13 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params, const voi
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
   uint8_t *support = (uint8_t *)(ws + L.support);
-  MLS_HIP(mls::launch_knn(grid->g.view, qv, params->k, params->support_radius_h, nbr, support,
-                          out_neighbors, nullptr, s));
-  MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
-                                  params->min_support, nbr, support, out_points, out_status, s));
+  if (stages & MLS_STAGE_SEARCH)
+    MLS_HIP(mls::launch_knn(grid->g.view, qv, params->k, params->support_radius_h, nbr, support,
+                            out_neighbors, nullptr, s));
+  if (stages & MLS_STAGE_FIT)
+    MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
+                                    params->min_support, nbr, support, out_points, out_status,
+                                    s));
   return MLS_OK;
 }
 

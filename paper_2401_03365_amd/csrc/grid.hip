@@ -262,18 +262,32 @@ __global__ __launch_bounds__(kThreads) void k_gather(const float *__restrict__ p
 }
 
 // ---- 5. cells -------------------------------------------------------------------------
-__device__ __forceinline__ bool is_run_start(const uint64_t *keys, int64_t s) {
+// A level-l cell is a run of equal (key >> 3l) in the sorted keys.
+__device__ __forceinline__ bool is_run_start(const uint64_t *keys, int64_t s, int level) {
   const uint64_t k = keys[s];
-  return k != kEmptyKey && (s == 0 || keys[s - 1] != k);
+  return k != kEmptyKey && (s == 0 || (keys[s - 1] >> (3 * level)) != (k >> (3 * level)));
 }
 
 __global__ __launch_bounds__(kThreads) void k_count_cells(const uint64_t *__restrict__ keys,
-                                                          int64_t n,
-                                                          unsigned long long *__restrict__ count) {
-  const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const bool start = s < n && is_run_start(keys, s);
-  const uint64_t m = __ballot(start);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
+                                                          int64_t n, int n_levels,
+                                                          unsigned long long *__restrict__ counts) {
+  __shared__ uint32_t part[kMaxLevels][kThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t c[kMaxLevels] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * kThreads)
+    for (int l = 0; l < n_levels; ++l) c[l] += is_run_start(keys, s, l) ? 1u : 0u;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    uint32_t v = c[l];
+    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
+    if (lane == 0) part[l][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxLevels && threadIdx.x < n_levels) {
+    uint32_t t = 0;
+    for (int i = 0; i < kThreads / 64; ++i) t += part[threadIdx.x][i];
+    if (t) atomicAdd(counts + threadIdx.x, (unsigned long long)t);
+  }
 }
 
 __global__ void k_table_fill(uint4 *__restrict__ table, uint64_t capacity) {
@@ -282,37 +296,43 @@ __global__ void k_table_fill(uint4 *__restrict__ table, uint64_t capacity) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_table_insert(const uint64_t *__restrict__ keys,
-                                                           int64_t n, uint4 *__restrict__ table,
-                                                           uint64_t mask) {
+                                                           int64_t n, int n_levels,
+                                                           uint4 *__restrict__ table,
+                                                           uint64_t mask, int shift) {
   const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (s >= n || !is_run_start(keys, s)) return;
-  const uint64_t key = keys[s];
-  // end of the run: exponential then binary search for the first larger key
-  int64_t lo = s, step = 1, hi;
-  for (;;) {
-    hi = lo + step;
-    if (hi >= n || keys[hi] != key) break;
-    lo = hi;
-    step <<= 1;
-  }
-  if (hi > n) hi = n;
-  while (hi - lo > 1) {  // keys[lo] == key, keys[hi] != key or hi == n
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (keys[mid] == key) lo = mid; else hi = mid;
-  }
-  const uint32_t count = (uint32_t)(hi - s);
-  uint64_t slot = hash64(key) & mask;
-  for (uint64_t probe = 0; probe <= mask; ++probe) {
-    unsigned long long *kp = reinterpret_cast<unsigned long long *>(table + slot);
-    const unsigned long long prev = atomicCAS(kp, (unsigned long long)kEmptyKey,
-                                              (unsigned long long)key);
-    if (prev == (unsigned long long)kEmptyKey) {
-      uint32_t *vp = reinterpret_cast<uint32_t *>(table + slot);
-      vp[2] = (uint32_t)s;
-      vp[3] = count;
-      return;
+  if (s >= n) return;
+  for (int l = 0; l < n_levels; ++l) {
+    if (!is_run_start(keys, s, l)) continue;
+    const int sh = 3 * l;
+    const uint64_t key = keys[s] >> sh;
+    // end of the run: exponential then binary search for the first larger key
+    int64_t lo = s, step = 1, hi;
+    for (;;) {
+      hi = lo + step;
+      if (hi >= n || (keys[hi] >> sh) != key) break;
+      lo = hi;
+      step <<= 1;
     }
-    slot = (slot + 1) & mask;
+    if (hi > n) hi = n;
+    while (hi - lo > 1) {  // keys[lo] in the run, keys[hi] past it (or hi == n)
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if ((keys[mid] >> sh) == key) lo = mid; else hi = mid;
+    }
+    const uint32_t count = (uint32_t)(hi - s);
+    const uint64_t tagged = key | ((uint64_t)l << kLevelShift);
+    uint64_t slot = hash_slot(tagged, shift);
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+      unsigned long long *kp = reinterpret_cast<unsigned long long *>(table + slot);
+      const unsigned long long prev = atomicCAS(kp, (unsigned long long)kEmptyKey,
+                                                (unsigned long long)tagged);
+      if (prev == (unsigned long long)kEmptyKey) {
+        uint32_t *vp = reinterpret_cast<uint32_t *>(table + slot);
+        vp[2] = (uint32_t)s;
+        vp[3] = count;
+        break;
+      }
+      slot = (slot + 1) & mask;
+    }
   }
 }
 
@@ -408,19 +428,23 @@ hipError_t launch_gather(const float *pts, const int32_t *vals, int64_t n, float
   return hipGetLastError();
 }
 
-hipError_t launch_count_cells(const uint64_t *keys, int64_t n, unsigned long long *count,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_count_cells, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, keys, n,
-                     count);
+hipError_t launch_count_cells(const uint64_t *keys, int64_t n, int n_levels,
+                              unsigned long long *counts, hipStream_t s) {
+  unsigned blocks = blocks_for(n, kThreads * 8);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_count_cells, dim3(blocks), dim3(kThreads), 0, s, keys, n, n_levels, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_build_table(const uint64_t *keys, int64_t n, uint4 *table, uint64_t capacity,
-                              hipStream_t s) {
+hipError_t launch_build_table(const uint64_t *keys, int64_t n, int n_levels, uint4 *table,
+                              uint64_t capacity, hipStream_t s) {
   hipLaunchKernelGGL(k_table_fill, dim3(blocks_for((int64_t)capacity, 256)), dim3(256), 0, s,
                      table, capacity);
+  int shift = 64;
+  for (uint64_t c = capacity; c > 1; c >>= 1) --shift;
   hipLaunchKernelGGL(k_table_insert, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, keys, n,
-                     table, capacity - 1);
+                     n_levels, table, capacity - 1, shift);
   return hipGetLastError();
 }
 

@@ -1,39 +1,56 @@
 // knn.hip -- exact k-nearest-neighbour search on the uniform grid.
 //
-// One wavefront per query; lanes range over candidate points. The k-nearest
-// set is defined on canonical FP64 keys
+// The k-nearest set is defined on canonical FP64 keys
 //     key = ((dx*dx + dy*dy) + dz*dz),  d = p - r,
-// each operation a binary64 round-to-nearest with no fused multiply-add, and
-// ties go to the smaller original index, so the set is unique and equal to a
-// brute-force search over the whole cloud. Keys of non-negative doubles order
-// like their bit patterns, so selection works on uint64.
+// each operation a binary64 round-to-nearest with no fused multiply-add (this
+// file is compiled with contraction off), ties to the smaller original index,
+// so the set is unique and equals a brute-force search over the whole cloud.
+// Keys of non-negative doubles order like their bit patterns.
 //
-// Search: the 3x3x3 block of cells around the query's cell first, then
-// shells of growing Chebyshev radius L. After each round the distance beta
-// from the query to the boundary of the visited box (minus a margin that
-// covers the rounding of the cell assignment) bounds every unvisited point
-// from below; the search stops when the k-th key is strictly below beta^2.
-// Beyond kMaxRing rings the cloud is scanned exhaustively. The running top-k
-// lives in one register slot per lane (lane j holds entry j); each batch of
-// new candidates is merged by finding the k-th smallest (key, index) pair with
-// a ballot/popcount bisection and compacting the survivors through LDS.
+// Work layout: one wavefront owns a chunk of consecutive queries in
+// processing order (Morton order of the grid for queries aligned with the
+// points), so consecutive queries usually fall in the same cell. The grid
+// indexes cells at several levels (edges c, 2c, 4c, 8c: a coarse cell is a
+// contiguous Morton range of the sorted points). For each query the wave
+// uses the 3x3x3 block of cells around the query's cell at a level chosen so
+// that the block both holds the k nearest and fits the candidate slots (the
+// level follows the previous query's k-th distance, so it adapts to the
+// local density). The block's candidates -- cell lookups, their prefix sum
+// and the candidate coordinates -- are gathered once into registers (lanes x
+// slots) and reused by every following query of the chunk in the same cell;
+// per query only the FP64 keys and the selection remain.
+//
+// Certification: the distance beta from the query to the boundary of the
+// visited box (faces beyond the cloud's grid count as infinitely far; a
+// margin of cell * 2^-20 covers the rounding of the cell assignment) bounds
+// every unvisited point from below, and the list is final once the k-th key
+// is strictly below beta^2. Queries that no level certifies take the
+// general path: shells of growing Chebyshev radius L around the query's
+// level-0 cell, then an exhaustive scan of the cloud beyond kMaxRing.
+//
+// Selection (k of up to 320 pairs): keys are bucketed by a monotone map
+// b = floor(key * scale) into 256 bins; an LDS histogram and its prefix sum
+// give the bin b* holding the k-th pair; bins below b* are kept and inside b*
+// the needed number of smallest pairs is found by ranking (small bins) or by
+// bisection on the key bits and then on the index (large bins, i.e. ties).
 #include "mls_internal.h"
 
 namespace mls {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kSlots = 4;      // slot 0 = running top-k, slots 1..3 = new candidates
-constexpr int kNew = (kSlots - 1) * 64;
+constexpr int kSlots = 5;                 // slot 0 = running top-k, 1..4 = candidates
+constexpr int kNew = (kSlots - 1) * 64;   // candidates per batch
 constexpr int kMaxRing = 12;
+constexpr int kChunk = 64;                // consecutive queries per wave task
 
 struct alignas(16) WaveLds {
-  uint32_t cstart[64];
-  uint32_t cexcl[65];
-  uint32_t pad[3];
+  uint32_t cstart[128];
+  uint32_t cexcl[128];
   uint64_t ck[64];
   int32_t cpos[64];
   int32_t cidx[64];
+  uint32_t hist[256];
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -42,10 +59,9 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Canonical squared distance; contraction must stay off so that the rounding
-// sequence is exactly sub, mul, mul, mul, add, add.
+// Canonical squared distance: sub, mul, mul, mul, add, add, no contraction.
 __device__ __forceinline__ double canon_key(double px, double py, double pz, double rx,
-                                                      double ry, double rz) {
+                                            double ry, double rz) {
 #pragma clang fp contract(off)
   const double dx = px - rx;
   const double dy = py - ry;
@@ -57,6 +73,7 @@ __device__ __forceinline__ double canon_key(double px, double py, double pz, dou
 }
 
 __device__ __forceinline__ uint64_t dbits(double d) { return (uint64_t)__double_as_longlong(d); }
+__device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 
 __device__ __forceinline__ bool pair_lt(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
   return ka < kb || (ka == kb && ia < ib);
@@ -68,156 +85,425 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   return (uint64_t)__shfl_xor((long long)v, m);
 }
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = shfl_xor_u64(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 struct Slots {
   uint64_t key[kSlots];
   int32_t pos[kSlots];
   int32_t idx[kSlots];
 };
 
-__device__ __forceinline__ uint32_t count_lt(const Slots &s, uint64_t x) {
-  uint32_t c = 0;
+// Among the entries flagged by `in`, keep the `need` smallest (key, index)
+// pairs: bisection on the key bits, then on the index among equal keys.
+__device__ void select_in_set(const Slots &s, const bool in[kSlots], uint32_t need,
+                              bool keep[kSlots]) {
+  uint64_t mx = 0;
 #pragma unroll
-  for (int i = 0; i < kSlots; ++i) c += popc(__ballot(s.key[i] < x));
-  return c;
+  for (int i = 0; i < kSlots; ++i) mx = (in[i] && s.key[i] > mx) ? s.key[i] : mx;
+  mx = wave_max_u64(mx);
+  uint64_t lo = 0, hi = mx + 1;
+  uint32_t clo = 0, chi = 0;
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) chi += popc(__ballot(in[i]));
+  while (hi - lo > 1 && chi - clo > 1) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) c += popc(__ballot(in[i] && s.key[i] < mid));
+    if (c < need) { lo = mid; clo = c; } else { hi = mid; chi = c; }
+  }
+  uint64_t K = lo;
+  if (hi - lo > 1) {  // exactly one flagged entry in [lo, hi): it is the need-th
+    uint64_t found = 0;
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i)
+      found = (in[i] && s.key[i] >= lo && s.key[i] < hi) ? s.key[i] : found;
+    K = wave_max_u64(found);
+  }
+  uint32_t c_lt = 0, c_le = 0;
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) {
+    c_lt += popc(__ballot(in[i] && s.key[i] < K));
+    c_le += popc(__ballot(in[i] && s.key[i] <= K));
+  }
+  const uint32_t at_k = need - c_lt;  // entries with key == K to keep
+  if (c_le - c_lt == at_k) {
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) keep[i] = in[i] && s.key[i] <= K;
+    return;
+  }
+  int64_t ilo = -1, ihi = 0x7fffffff;  // count(idx <= ilo) < at_k <= count(idx <= ihi)
+  while (ihi - ilo > 1) {
+    const int64_t mid = ilo + ((ihi - ilo) >> 1);
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i)
+      c += popc(__ballot(in[i] && s.key[i] == K && s.idx[i] <= mid));
+    if (c < at_k) ilo = mid; else ihi = mid;
+  }
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i)
+    keep[i] = in[i] && (s.key[i] < K || (s.key[i] == K && s.idx[i] <= (int32_t)ihi));
 }
 
-// Merge the new candidates (slots 1..) into the running top-k (slot 0,
-// lanes < ntop). Invalid entries carry key ~0. On return slot 0 holds
-// min(k, total) entries and ntop/kmax/imax describe it.
-__device__ void merge(Slots &s, int &ntop, int k, uint64_t &kmax, int32_t &imax, WaveLds &L,
-                      int lane) {
-  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+// Flags the min(k, total) smallest valid pairs. scale maps keys to buckets
+// (keys beyond 255/scale share the last bucket). Returns the bucket holding
+// the k-th pair, or -1 when every valid entry is kept.
+__device__ int select_topk(const Slots &s, int k, double scale, WaveLds &L, int lane,
+                           bool keep[kSlots], uint32_t *total_out) {
   uint32_t total = 0;
 #pragma unroll
   for (int i = 0; i < kSlots; ++i) total += popc(__ballot(s.key[i] != kEmptyKey));
-  bool keep[kSlots];
+  *total_out = total;
   if ((int)total <= k) {
 #pragma unroll
     for (int i = 0; i < kSlots; ++i) keep[i] = s.key[i] != kEmptyKey;
-  } else {
-    // k-th smallest key value K: count_lt(K) < k <= count_lt(K + 1)
-    uint64_t mx = 0;
-#pragma unroll
-    for (int i = 0; i < kSlots; ++i)
-      if (s.key[i] != kEmptyKey && s.key[i] > mx) mx = s.key[i];
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint64_t o = shfl_xor_u64(mx, off);
-      mx = o > mx ? o : mx;
-    }
-    uint64_t lo = 0, hi = mx + 1;
-    uint32_t clo = 0, chi = total;
-    while (hi - lo > 1 && chi - clo > 1) {
-      const uint64_t mid = lo + ((hi - lo) >> 1);
-      const uint32_t c = count_lt(s, mid);
-      if ((int)c < k) { lo = mid; clo = c; } else { hi = mid; chi = c; }
-    }
-    uint64_t K = lo;
-    if (hi - lo > 1) {
-      // exactly one entry in [lo, hi): it is the k-th
-      uint64_t found = 0;
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i)
-        if (s.key[i] >= lo && s.key[i] < hi) found = s.key[i];
-      for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = shfl_xor_u64(found, off);
-        found = o > found ? o : found;
-      }
-      K = found;
-    }
-    const uint32_t c_lt = count_lt(s, K);
-    const uint32_t c_le = count_lt(s, K + 1);
-    const uint32_t need = (uint32_t)k - c_lt;  // entries with key == K to keep
-    if (c_le - c_lt == need) {
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i) keep[i] = s.key[i] <= K;
-    } else {
-      // ties at K: keep the `need` smallest original indices
-      int64_t ilo = -1, ihi = 0x7fffffff;  // count(idx <= ilo) < need <= count(idx <= ihi)
-      while (ihi - ilo > 1) {
-        const int64_t mid = ilo + ((ihi - ilo) >> 1);
-        uint32_t c = 0;
-#pragma unroll
-        for (int i = 0; i < kSlots; ++i) c += popc(__ballot(s.key[i] == K && s.idx[i] <= mid));
-        if (c < need) ilo = mid; else ihi = mid;
-      }
-#pragma unroll
-      for (int i = 0; i < kSlots; ++i)
-        keep[i] = s.key[i] < K || (s.key[i] == K && s.idx[i] <= (int32_t)ihi);
-    }
+    return -1;
   }
-  // compact kept entries into LDS, slot-major then lane order
+  reinterpret_cast<uint4 *>(L.hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
+  wave_sync();
+  int bkt[kSlots];
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) {
+    const bool v = s.key[i] != kEmptyKey;
+    const double x = bitsd(v ? s.key[i] : 0ull) * scale;
+    const int b = x < 255.0 ? (int)x : 255;
+    bkt[i] = v ? b : 256;
+    if (v) atomicAdd(&L.hist[b], 1u);
+  }
+  wave_sync();
+  const uint4 hv = reinterpret_cast<const uint4 *>(L.hist)[lane];
+  const uint32_t s4 = hv.x + hv.y + hv.z + hv.w;
+  uint32_t incl = s4;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+    incl += (lane >= off) ? y : 0u;
+  }
+  const uint32_t e0 = incl - s4, e1 = e0 + hv.x, e2 = e1 + hv.y, e3 = e2 + hv.z;
+  const uint32_t ku = (uint32_t)k;
+  int mybin = -1;
+  uint32_t mybelow = 0, mycnt = 0;
+  if (e0 < ku && ku <= e1) { mybin = 0; mybelow = e0; mycnt = hv.x; }
+  if (e1 < ku && ku <= e2) { mybin = 1; mybelow = e1; mycnt = hv.y; }
+  if (e2 < ku && ku <= e3) { mybin = 2; mybelow = e2; mycnt = hv.z; }
+  if (e3 < ku && ku <= incl) { mybin = 3; mybelow = e3; mycnt = hv.w; }
+  const uint64_t who = __ballot(mybin >= 0);
+  const int src = (int)__builtin_ctzll(who);
+  const int bstar = 4 * src + __builtin_amdgcn_readlane(mybin, src);
+  const uint32_t below = (uint32_t)__builtin_amdgcn_readlane((int)mybelow, src);
+  const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)mycnt, src);
+  const uint32_t need = ku - below;
+  bool in[kSlots];
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) in[i] = bkt[i] == bstar;
+  if (need == m) {
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) keep[i] = bkt[i] <= bstar;
+    return bstar;
+  }
+  bool kin[kSlots];
+  if (m <= 16) {
+    // rank every entry of the bucket against the others
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) kin[i] = false;
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+      uint64_t mask = __ballot(in[sl]);
+      while (mask) {
+        const int l = (int)__builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint64_t ke = readlane_u64(s.key[sl], l);
+        const int32_t ie = __builtin_amdgcn_readlane(s.idx[sl], l);
+        uint32_t rank = 0;
+#pragma unroll
+        for (int i = 0; i < kSlots; ++i)
+          rank += popc(__ballot(in[i] && pair_lt(s.key[i], s.idx[i], ke, ie)));
+        kin[sl] = (lane == l) ? (rank < need) : kin[sl];
+      }
+    }
+  } else {
+    select_in_set(s, in, need, kin);
+  }
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) keep[i] = bkt[i] < bstar || kin[i];
+  return bstar;
+}
+
+// Moves the kept entries into slot 0 (lanes 0..count-1) and clears the
+// candidate slots' keys (their positions and indices stay). Returns the count.
+__device__ int compact(Slots &s, const bool keep[kSlots], WaveLds &L, int lane) {
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t base = 0;
 #pragma unroll
   for (int i = 0; i < kSlots; ++i) {
-    const uint64_t m = __ballot(keep[i]);
+    const uint64_t msk = __ballot(keep[i]);
     if (keep[i]) {
-      const uint32_t o = base + popc(m & lt_mask);
+      const uint32_t o = base + popc(msk & lt_mask);
       L.ck[o] = s.key[i];
       L.cpos[o] = s.pos[i];
       L.cidx[o] = s.idx[i];
     }
-    base += popc(m);
+    base += popc(msk);
   }
   wave_sync();
-  ntop = (int)base;
-  {
-    const bool have = lane < ntop;
-    const uint64_t ck = L.ck[lane];
-    const int32_t cp = L.cpos[lane], ci = L.cidx[lane];
-    s.key[0] = have ? ck : kEmptyKey;
-    s.pos[0] = have ? cp : 0;
-    s.idx[0] = have ? ci : 0x7fffffff;
-  }
+  const int ntop = (int)base;
+  const bool have = lane < ntop;
+  const uint64_t ck = L.ck[lane];
+  const int32_t cp = L.cpos[lane], ci = L.cidx[lane];
   wave_sync();
+  s.key[0] = have ? ck : kEmptyKey;
+  s.pos[0] = have ? cp : 0;
+  s.idx[0] = have ? ci : 0x7fffffff;
 #pragma unroll
   for (int i = 1; i < kSlots; ++i) s.key[i] = kEmptyKey;
-  if (ntop == k) {
-    uint64_t mk = lane < ntop ? s.key[0] : 0;
-    int32_t mi = lane < ntop ? s.idx[0] : -1;
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint64_t ok = shfl_xor_u64(mk, off);
-      const int32_t oi = __shfl_xor(mi, off);
-      const bool t = pair_lt(mk, mi, ok, oi);
-      mk = t ? ok : mk;
-      mi = t ? oi : mi;
-    }
-    kmax = mk;
-    imax = mi;
-  }
+  return ntop;
 }
 
-// Load candidate `ci` (an index into the batch's concatenated cell ranges)
-// into slot `sl` if it can enter the top-k.
-__device__ __forceinline__ void load_candidate(const GridView &g, const WaveLds &L, int64_t ci,
-                                               int64_t total, bool from_cells, int64_t range_base,
-                                               double rx, double ry, double rz, int ntop, int k,
-                                               uint64_t kmax, int32_t imax, Slots &s, int sl) {
-  s.key[sl] = kEmptyKey;
-  if (ci >= total) return;
-  int64_t pos;
-  if (from_cells) {
-    int lo = 0, hi = 64;  // largest c with cexcl[c] <= ci
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if ((int64_t)L.cexcl[mid] <= ci) lo = mid; else hi = mid;
-    }
-    pos = (int64_t)L.cstart[lo] + (ci - (int64_t)L.cexcl[lo]);
-  } else {
-    pos = range_base + ci;
+// Largest (key, index) pair of the running top-k.
+__device__ void top_max(const Slots &s, int ntop, int lane, uint64_t &kmax, int32_t &imax) {
+  uint64_t mk = lane < ntop ? s.key[0] : 0;
+  int32_t mi = lane < ntop ? s.idx[0] : -1;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t ok = shfl_xor_u64(mk, off);
+    const int32_t oi = __shfl_xor(mi, off);
+    const bool t = pair_lt(mk, mi, ok, oi);
+    mk = t ? ok : mk;
+    mi = t ? oi : mi;
   }
-  if (pos < 0 || pos >= g.n_points) return;
-  const float4 P = g.pts[pos];
-  const uint64_t key = dbits(canon_key((double)P.x, (double)P.y, (double)P.z, rx, ry, rz));
+  kmax = mk;
+  imax = mi;
+}
+
+// Distance from r to the boundary of the box of cells [c0 - L, c0 + L]
+// (faces beyond the cloud's grid are at infinity), minus the assignment
+// margin. Returns +inf when the box covers the whole grid.
+__device__ __forceinline__ double box_clearance(const CloudDev &cd, const double r[3],
+                                                const int32_t c0[3], int L, int level = 0) {
+  double beta = __longlong_as_double(0x7ff0000000000000ll);
+  const double cell = ldexp(cd.cell, level);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int32_t lo = c0[a] - L, hi = c0[a] + L;
+    const int32_t dims = ((cd.dims[a] - 1) >> level) + 1;
+    if (lo > 0) beta = fmin(beta, r[a] - (cd.origin[a] + (double)lo * cell));
+    if (hi < dims - 1) beta = fmin(beta, (cd.origin[a] + (double)(hi + 1) * cell) - r[a]);
+  }
+  if (!isinf(beta)) beta -= cell * 0x1p-20;
+  return beta;
+}
+
+// Squared bound a k-th key must stay strictly below: beta^2 rounded down.
+__device__ __forceinline__ double cert_bound(double beta) {
+  if (isinf(beta)) return beta;
+  return beta > 0.0 ? beta * beta * (1.0 - 0x1p-40) : 0.0;
+}
+
+// Sorted position of candidate ci of the concatenated cell ranges staged in
+// LDS (128 entries: exclusive prefix `cexcl`, starts `cstart`).
+__device__ __forceinline__ int32_t cand_pos(const WaveLds &L, int32_t ci) {
+  int lo = 0, hi = 128;  // largest c with cexcl[c] <= ci
+#pragma unroll
+  for (int it = 0; it < 7; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const bool le = (int32_t)L.cexcl[mid] <= ci;
+    lo = le ? mid : lo;
+    hi = le ? hi : mid;
+  }
+  return (int32_t)L.cstart[lo] + (ci - (int32_t)L.cexcl[lo]);
+}
+
+__device__ __forceinline__ int2 lookup_if(const GridView &g, int cloud, const CloudDev &cd,
+                                          bool has, int32_t cx, int32_t cy, int32_t cz,
+                                          int level) {
+  if (has && cx >= 0 && cy >= 0 && cz >= 0 && cx <= ((cd.dims[0] - 1) >> level) &&
+      cy <= ((cd.dims[1] - 1) >> level) && cz <= ((cd.dims[2] - 1) >> level))
+    return lookup_cell(g, level_cell_key(cloud, cx, cy, cz, g.morton_bits, level));
+  return make_int2(0, 0);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, off);
+    x += (lane >= off) ? y : 0u;
+  }
+  return x;
+}
+
+// Stages up to 128 cell ranges (entry lane and entry 64 + lane) and their
+// exclusive prefix in LDS; returns the candidate total.
+__device__ __forceinline__ int32_t stage_ranges(int2 a, int2 b, WaveLds &L, int lane) {
+  const uint32_t xa = wave_incl_scan((uint32_t)a.y, lane);
+  const uint32_t ta = (uint32_t)__shfl((int)xa, 63);
+  const uint32_t xb = wave_incl_scan((uint32_t)b.y, lane);
+  const uint32_t tb = (uint32_t)__shfl((int)xb, 63);
+  wave_sync();
+  L.cstart[lane] = (uint32_t)a.x;
+  L.cexcl[lane] = xa - (uint32_t)a.y;
+  L.cstart[64 + lane] = (uint32_t)b.x;
+  L.cexcl[64 + lane] = ta + xb - (uint32_t)b.y;
+  wave_sync();
+  return (int32_t)(ta + tb);
+}
+
+// One cell per lane (count 0 for lanes without a cell).
+__device__ __forceinline__ int32_t stage_cells(const GridView &g, int cloud, const CloudDev &cd,
+                                               bool has, int32_t cx, int32_t cy, int32_t cz,
+                                               WaveLds &L, int lane, int level = 0) {
+  return stage_ranges(lookup_if(g, cloud, cd, has, cx, cy, cz, level), make_int2(0, 0), L, lane);
+}
+
+// The (2 half + 1)^3 block of level-`level` cells around cell cl (half 1 or 2).
+__device__ __forceinline__ int32_t stage_block(const GridView &g, int cloud, const CloudDev &cd,
+                                               const int32_t cl[3], int half, int level,
+                                               WaveLds &L, int lane) {
+  const int w = 2 * half + 1;
+  const int n = w * w * w;
+  int2 ab[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int t = lane + 64 * e;
+    const int dx = t % w - half, dy = (t / w) % w - half, dz = t / (w * w) - half;
+    ab[e] = lookup_if(g, cloud, cd, t < n, cl[0] + dx, cl[1] + dy, cl[2] + dz, level);
+  }
+  return stage_ranges(ab[0], ab[1], L, lane);
+}
+
+// Candidate at sorted position pos into slot sl if it can still enter the
+// top-k (branch-free: position and index are always written, only the key
+// marks the entry valid).
+__device__ __forceinline__ void put_candidate(const GridView &g, int32_t pos, bool present,
+                                              const double r[3], int ntop, int k, uint64_t kmax,
+                                              int32_t imax, Slots &s, int sl) {
+  float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (present) P = g.pts[pos];
+  const uint64_t key = dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]));
   const int32_t idx = __float_as_int(P.w);
-  // branch-free: position and index are written unconditionally and only the
-  // key marks the entry valid
-  const bool take = (ntop < k) || pair_lt(key, idx, kmax, imax);
-  s.pos[sl] = (int32_t)pos;
+  const bool take = present && ((ntop < k) || pair_lt(key, idx, kmax, imax));
+  s.pos[sl] = pos;
   s.idx[sl] = idx;
   s.key[sl] = take ? key : kEmptyKey;
 }
 
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_knn(GridView g, QueryView qv, int32_t k,
+// Merge the filled candidate slots into the top-k (general path).
+__device__ void merge_general(Slots &s, int &ntop, int k, uint64_t &kmax, int32_t &imax,
+                              WaveLds &L, int lane) {
+  uint64_t mx;
+  if (ntop == k) {
+    mx = kmax;  // new entries were filtered below the current k-th pair
+  } else {
+    mx = 0;
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) mx = (s.key[i] != kEmptyKey && s.key[i] > mx) ? s.key[i] : mx;
+    mx = wave_max_u64(mx);
+  }
+  const double scale = 255.99 / fmax(bitsd(mx), 1e-300);
+  bool keep[kSlots];
+  uint32_t total;
+  select_topk(s, k, scale, L, lane, keep, &total);
+  ntop = compact(s, keep, L, lane);
+  if (ntop == k) top_max(s, ntop, lane, kmax, imax);
+}
+
+// General search for one query from scratch: rings of growing Chebyshev
+// radius around the query's cell at the coarsest level, then the exhaustive
+// scan. Returns ntop.
+__device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, const double r[3],
+                              const int32_t cq[3], int k, Slots &s, WaveLds &L, int lane) {
+  const int lev = g.n_levels - 1;
+  const double cellc = ldexp(cd.cell, lev);
+  int32_t c0[3];
+  int32_t lmin = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // floor division of the level-0 cell by 2^lev (cq may be negative)
+    c0[a] = cq[a] >= 0 ? (cq[a] >> lev) : -((-cq[a] + (1 << lev) - 1) >> lev);
+    const int32_t dims = ((cd.dims[a] - 1) >> lev) + 1;
+    lmin = max(lmin, max(-c0[a], c0[a] - (dims - 1)));
+  }
+  (void)cellc;
+#pragma unroll
+  for (int i = 0; i < kSlots; ++i) { s.key[i] = kEmptyKey; s.pos[i] = 0; s.idx[i] = 0x7fffffff; }
+  int ntop = 0;
+  uint64_t kmax = kEmptyKey;
+  int32_t imax = 0x7fffffff;
+  bool brute = lmin > kMaxRing;
+  const int L0 = lmin < 1 ? 1 : lmin;
+  bool done = false;
+  for (int ring = L0; !done && !brute; ++ring) {
+    const int w = 2 * ring + 1;
+    const int32_t ncells = w * w * w;
+    for (int32_t t0 = 0; t0 < ncells; t0 += 64) {
+      const int32_t t = t0 + lane;
+      const int32_t dx = t % w - ring, dy = (t / w) % w - ring, dz = t / (w * w) - ring;
+      const int cheb = max(abs(dx), max(abs(dy), abs(dz)));
+      const bool has = t < ncells && (ring == L0 || cheb == ring);
+      const int32_t total =
+          stage_cells(g, cloud, cd, has, c0[0] + dx, c0[1] + dy, c0[2] + dz, L, lane, lev);
+      for (int32_t b0 = 0; b0 < total; b0 += kNew) {
+#pragma unroll
+        for (int sl = 1; sl < kSlots; ++sl) {
+          const int32_t ci = b0 + (sl - 1) * 64 + lane;
+          const bool present = ci < total;
+          const int32_t pos = present ? cand_pos(L, ci) : 0;
+          const bool inb = pos >= 0 && (int64_t)pos < g.n_points;
+          put_candidate(g, inb ? pos : 0, present && inb, r, ntop, k, kmax, imax, s, sl);
+        }
+        bool any = false;
+#pragma unroll
+        for (int sl = 1; sl < kSlots; ++sl) any |= __ballot(s.key[sl] != kEmptyKey) != 0ull;
+        if (any) merge_general(s, ntop, k, kmax, imax, L, lane);
+      }
+    }
+    const double beta = box_clearance(cd, r, c0, ring, lev);
+    if (isinf(beta)) {
+      done = true;  // every cell of the cloud visited
+    } else {
+      if (ntop == k && bitsd(kmax) < cert_bound(beta)) done = true;
+      if (!done && ring >= kMaxRing) brute = true;
+    }
+  }
+  if (brute) {
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) { s.key[i] = kEmptyKey; s.idx[i] = 0x7fffffff; }
+    ntop = 0;
+    kmax = kEmptyKey;
+    imax = 0x7fffffff;
+    const int64_t total = cd.send - cd.sbegin;
+    for (int64_t b0 = 0; b0 < total; b0 += kNew) {
+#pragma unroll
+      for (int sl = 1; sl < kSlots; ++sl) {
+        const int64_t ci = b0 + (sl - 1) * 64 + lane;
+        const bool present = ci < total;
+        put_candidate(g, present ? (int32_t)(cd.sbegin + ci) : 0, present, r, ntop, k, kmax,
+                      imax, s, sl);
+      }
+      bool any = false;
+#pragma unroll
+      for (int sl = 1; sl < kSlots; ++sl) any |= __ballot(s.key[sl] != kEmptyKey) != 0ull;
+      if (any) merge_general(s, ntop, k, kmax, imax, L, lane);
+    }
+  }
+  return ntop;
+}
+
+// Block options (level, half-width), in increasing block volume
+// ((2 half + 1) 2^level)^3: each guarantees a clearance of about half * 2^level
+// cells of the finest level.
+__constant__ int8_t kOptLevel[2 * kMaxLevels] = {0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 5, 5, 6, 6, 7, 7};
+__constant__ int8_t kOptHalf[2 * kMaxLevels] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
+
+__global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
                                                             double support_r_h,
                                                             int32_t *__restrict__ nbr,
                                                             uint8_t *__restrict__ support,
@@ -227,157 +513,212 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_knn(GridView g, QueryVi
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   WaveLds &L = lds[wv];
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t p = (int64_t)blockIdx.x * kWavesPerBlock + wv; p < qv.n; p += nwaves) {
-    int64_t qi;
-    if (qv.aligned) qi = __float_as_int(g.pts[p].w);
-    else qi = qv.order ? qv.order[p] : p;
-    qi = __builtin_amdgcn_readfirstlane((int)qi);
-    double rx, ry, rz;
-    if (qv.is_f64) {
-      const double *q = (const double *)qv.q + 3 * qi;
-      rx = q[0]; ry = q[1]; rz = q[2];
-    } else {
-      const float *q = (const float *)qv.q + 3 * qi;
-      rx = q[0]; ry = q[1]; rz = q[2];
-    }
-    const int cloud = qv.qcloud ? qv.qcloud[qi] : 0;
-    const CloudDev &cd = g.clouds[cloud];
-    const bool finite = isfinite(rx) && isfinite(ry) && isfinite(rz);
-
+  const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
+  const int nopt = 2 * g.n_levels;
+  for (int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wv; task < nchunks;
+       task += (int64_t)gridDim.x * kWavesPerBlock) {
+    // cache of the staged block: its cell, option and cloud, the candidate
+    // count and the candidate coordinates (positions and indices live in the
+    // candidate slots of s)
+    int32_t cc0[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    int ccloud = -1, copt = -1;
+    int32_t ncand = -1;
+    bool cached = false;  // candidate slots hold the staged block
+    double rho_est = 0.0;  // k-th distance of the previous query of the chunk
+    float cx[kSlots], cy[kSlots], cz[kSlots];
     Slots s;
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i) { s.key[i] = kEmptyKey; s.pos[i] = 0; s.idx[i] = 0x7fffffff; }
-    int ntop = 0;
-    uint64_t kmax = kEmptyKey;
-    int32_t imax = 0x7fffffff;
-
-    if (finite && cd.send > cd.sbegin) {
-      const double r[3] = {rx, ry, rz};
-      int64_t c0[3];
-      int64_t lmin = 0;
-      for (int a = 0; a < 3; ++a) {
-        int64_t t = cell_coord(r[a], cd.origin[a], cd.inv_cell);
-        t = t < -(1ll << 40) ? -(1ll << 40) : (t > (1ll << 40) ? (1ll << 40) : t);
-        c0[a] = t;
-        int64_t out_lo = -t, out_hi = t - (cd.dims[a] - 1);
-        lmin = max(lmin, max(out_lo, out_hi));
+    for (int i = 0; i < kSlots; ++i) {
+      s.key[i] = kEmptyKey; s.pos[i] = 0; s.idx[i] = 0x7fffffff;
+      cx[i] = cy[i] = cz[i] = 0.f;
+    }
+    const int64_t pend = min((task + 1) * kChunk, qv.n);
+    for (int64_t p = task * kChunk; p < pend; ++p) {
+      int64_t qi;
+      if (qv.aligned) qi = __float_as_int(g.pts[p].w);
+      else qi = qv.order ? qv.order[p] : p;
+      qi = __builtin_amdgcn_readfirstlane((int)qi);
+      double r[3];
+      if (qv.is_f64) {
+        const double *q = (const double *)qv.q + 3 * qi;
+        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+      } else {
+        const float *q = (const float *)qv.q + 3 * qi;
+        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
       }
-      bool brute = lmin > kMaxRing;
-      int L0 = (int)(lmin < 1 ? 1 : lmin);
-      bool done = false;
-      for (int ring = L0; !done && !brute; ++ring) {
-        // cells of this round: the whole box at the first round, a shell after
-        const int w = 2 * ring + 1;
-        const int64_t ncand_cells = (int64_t)w * w * w;
-        for (int64_t t0 = 0; t0 < ncand_cells; t0 += 64) {
-          const int64_t t = t0 + lane;
-          int2 sc = make_int2(0, 0);
-          if (t < ncand_cells) {
-            const int dx = (int)(t % w) - ring;
-            const int dy = (int)((t / w) % w) - ring;
-            const int dz = (int)(t / ((int64_t)w * w)) - ring;
-            const int cheb = max(abs(dx), max(abs(dy), abs(dz)));
-            const int64_t cx = c0[0] + dx, cy = c0[1] + dy, cz = c0[2] + dz;
-            const bool in_round = (ring == L0) || cheb == ring;
-            if (in_round && cx >= 0 && cy >= 0 && cz >= 0 && cx < cd.dims[0] && cy < cd.dims[1] &&
-                cz < cd.dims[2])
-              sc = lookup_cell(g, cell_key(cloud, (int)cx, (int)cy, (int)cz, g.morton_bits));
-          }
-          // exclusive scan of counts over the wave
-          uint32_t x = (uint32_t)sc.y;
-          for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = (uint32_t)__shfl_up((int)x, off);
-            if (lane >= off) x += y;
-          }
-          const uint32_t total = (uint32_t)__shfl((int)x, 63);
-          if (total == 0) continue;
-          L.cstart[lane] = (uint32_t)sc.x;
-          L.cexcl[lane] = x - (uint32_t)sc.y;
-          wave_sync();
-          for (int64_t b0 = 0; b0 < total; b0 += kNew) {
+      const int cloud = __builtin_amdgcn_readfirstlane(qv.qcloud ? qv.qcloud[qi] : 0);
+      const CloudDev &cd = g.clouds[cloud];
+      const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
+      int ntop = 0;
+      if (finite && cd.send > cd.sbegin) {
+        int32_t c0[3];
+        int32_t lmin = 0;
 #pragma unroll
-            for (int sl = 1; sl < kSlots; ++sl)
-              load_candidate(g, L, b0 + (sl - 1) * 64 + lane, total, true, 0, rx, ry, rz, ntop, k,
-                             kmax, imax, s, sl);
-            bool any = false;
-#pragma unroll
-            for (int sl = 1; sl < kSlots; ++sl) any |= __ballot(s.key[sl] != kEmptyKey) != 0ull;
-            if (any) merge(s, ntop, k, kmax, imax, L, lane);
-          }
-          wave_sync();
-        }
-        // termination: k-th key strictly below the squared distance to the
-        // unvisited region (minus the cell-assignment margin)
-        double beta = __longlong_as_double(0x7ff0000000000000ll);  // +inf
         for (int a = 0; a < 3; ++a) {
-          const int64_t lo_cell = c0[a] - ring, hi_cell = c0[a] + ring;
-          if (lo_cell > 0) beta = fmin(beta, r[a] - (cd.origin[a] + (double)lo_cell * cd.cell));
-          if (hi_cell < cd.dims[a] - 1)
-            beta = fmin(beta, (cd.origin[a] + (double)(hi_cell + 1) * cd.cell) - r[a]);
+          double t = floor((r[a] - cd.origin[a]) * cd.inv_cell);
+          t = fmin(fmax(t, -1073741824.0), 1073741824.0);
+          c0[a] = (int32_t)t;
+          lmin = max(lmin, max(-c0[a], c0[a] - (cd.dims[a] - 1)));
         }
-        if (isinf(beta)) {
-          done = true;  // every cell of the cloud visited
-        } else {
-          beta -= cd.cell * 0x1p-20;
-          if (ntop == k && beta > 0.0) {
-            const double bound = beta * beta * (1.0 - 0x1p-40);
-            if (__longlong_as_double((long long)kmax) < bound) done = true;
+        bool solved = false;
+        if (lmin == 0) {
+          double target = 1.05 * rho_est;
+          for (int att = 0; att < 2 * kMaxLevels + 2 && !solved; ++att) {
+            // smallest block whose clearance (half-width plus the query's
+            // interior clearance in its cell) reaches the target
+            int opt = nopt - 1;
+            for (int o = 0; o < nopt; ++o) {
+              const int l = kOptLevel[o];
+              const double c = ldexp(cd.cell, l);
+              double f = c;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const double lo = cd.origin[a] + (double)(c0[a] >> l) * c;
+                f = fmin(f, fmin(r[a] - lo, lo + c - r[a]));
+              }
+              if ((double)kOptHalf[o] * c + fmax(f, 0.0) >= target) { opt = o; break; }
+            }
+            const int lt = kOptLevel[opt], half = kOptHalf[opt];
+            const int32_t cl[3] = {c0[0] >> lt, c0[1] >> lt, c0[2] >> lt};
+            if (cl[0] != cc0[0] || cl[1] != cc0[1] || cl[2] != cc0[2] || cloud != ccloud ||
+                opt != copt) {
+              // stage the block (and cache its candidates when they fit)
+              cc0[0] = cl[0]; cc0[1] = cl[1]; cc0[2] = cl[2];
+              ccloud = cloud;
+              copt = opt;
+              ncand = stage_block(g, cloud, cd, cl, half, lt, L, lane);
+              cached = ncand <= kNew;
+              if (cached) {
+#pragma unroll
+                for (int sl = 1; sl < kSlots; ++sl) {
+                  if ((sl - 1) * 64 < ncand) {
+                    const int32_t ci = (sl - 1) * 64 + lane;
+                    int32_t pos = ci < ncand ? cand_pos(L, ci) : 0;
+                    pos = (pos >= 0 && (int64_t)pos < g.n_points) ? pos : 0;
+                    const float4 P = g.pts[pos];
+                    cx[sl] = P.x; cy[sl] = P.y; cz[sl] = P.z;
+                    s.pos[sl] = pos;
+                    s.idx[sl] = __float_as_int(P.w);
+                  }
+                }
+              }
+            }
+            const double beta = box_clearance(cd, r, cl, half, lt);
+            const double bound = cert_bound(beta);
+            const bool inf = isinf(bound);
+            if (ncand < k && !inf) {
+              // too few points in the block: need a wider one
+              if (opt == nopt - 1) break;
+              target = fmax(target, 1.5 * fmax(beta, 0.0) + 1e-300);
+              continue;
+            }
+            uint64_t kmax = kEmptyKey;
+            int32_t imax = 0x7fffffff;
+            bool exact_max = false;
+            if (cached) {
+#pragma unroll
+              for (int sl = 1; sl < kSlots; ++sl) {
+                if ((sl - 1) * 64 < ncand) {
+                  const bool present = (sl - 1) * 64 + lane < ncand;
+                  const uint64_t key = dbits(canon_key((double)cx[sl], (double)cy[sl],
+                                                       (double)cz[sl], r[0], r[1], r[2]));
+                  s.key[sl] = present ? key : kEmptyKey;
+                } else {
+                  s.key[sl] = kEmptyKey;
+                }
+              }
+              s.key[0] = kEmptyKey;
+              double scale;
+              if (inf) {
+                uint64_t mx = 0;
+#pragma unroll
+                for (int i = 1; i < kSlots; ++i)
+                  mx = (s.key[i] != kEmptyKey && s.key[i] > mx) ? s.key[i] : mx;
+                scale = 255.99 / fmax(bitsd(wave_max_u64(mx)), 1e-300);
+              } else {
+                scale = 255.99 / fmax(bound, 1e-300);
+              }
+              bool keep[kSlots];
+              uint32_t total;
+              const int bstar = select_topk(s, k, scale, L, lane, keep, &total);
+              ntop = compact(s, keep, L, lane);
+              if (bstar >= 0 && bstar < 255 && !inf) {
+                kmax = dbits((double)(bstar + 1) / scale);  // upper bound of the k-th key
+              } else {
+                top_max(s, ntop, lane, kmax, imax);
+                exact_max = true;
+              }
+            } else {
+              // more candidates than slots: batches from the staged ranges
+              ntop = 0;
+#pragma unroll
+              for (int i = 0; i < kSlots; ++i) s.key[i] = kEmptyKey;
+              for (int32_t b0 = 0; b0 < ncand; b0 += kNew) {
+#pragma unroll
+                for (int sl = 1; sl < kSlots; ++sl) {
+                  const int32_t ci = b0 + (sl - 1) * 64 + lane;
+                  const bool present = ci < ncand;
+                  const int32_t pos = present ? cand_pos(L, ci) : 0;
+                  const bool inb = pos >= 0 && (int64_t)pos < g.n_points;
+                  put_candidate(g, inb ? pos : 0, present && inb, r, ntop, k, kmax, imax, s, sl);
+                }
+                bool any = false;
+#pragma unroll
+                for (int sl = 1; sl < kSlots; ++sl) any |= __ballot(s.key[sl] != kEmptyKey) != 0ull;
+                if (any) merge_general(s, ntop, k, kmax, imax, L, lane);
+              }
+              if (ntop == k) exact_max = true;
+            }
+            const bool done = ntop == k ? (inf || bitsd(kmax) < bound) : inf;
+            if (done) {
+              solved = true;
+              rho_est = ntop == k ? sqrt(bitsd(kmax)) : 0.0;
+            } else {
+              if (opt == nopt - 1) break;
+              // the block holds k points within sqrt(kmax): a clearance above
+              // that certifies
+              const double rk = exact_max ? sqrt(bitsd(kmax)) : sqrt(fmax(bound, 0.0));
+              target = fmax(1.05 * rk, 1.05 * sqrt(fmax(bound, 0.0)));
+            }
           }
-          if (!done && ring >= kMaxRing) brute = true;
+        }
+        if (!solved) {
+          ntop = search_general(g, cloud, cd, r, c0, k, s, L, lane);
+          cc0[0] = INT32_MIN;  // the general path reused the candidate slots
+          copt = -1;
+          cached = false;
         }
       }
-      if (brute) {
-        // exhaustive scan of the cloud's sorted range
-#pragma unroll
-        for (int i = 0; i < kSlots; ++i) { s.key[i] = kEmptyKey; s.idx[i] = 0x7fffffff; }
-        ntop = 0;
-        kmax = kEmptyKey;
-        imax = 0x7fffffff;
-        const int64_t total = cd.send - cd.sbegin;
-        for (int64_t b0 = 0; b0 < total; b0 += kNew) {
-#pragma unroll
-          for (int sl = 1; sl < kSlots; ++sl)
-            load_candidate(g, L, b0 + (sl - 1) * 64 + lane, total, false, cd.sbegin, rx, ry, rz,
-                           ntop, k, kmax, imax, s, sl);
-          bool any = false;
-#pragma unroll
-          for (int sl = 1; sl < kSlots; ++sl) any |= __ballot(s.key[sl] != kEmptyKey) != 0ull;
-          if (any) merge(s, ntop, k, kmax, imax, L, lane);
-        }
-      }
-    }
 
-    // ascending (key, index) order of the top-k: bitonic sort across lanes
-    uint64_t mk = s.key[0];
-    int32_t mi = s.idx[0], mp = s.pos[0];
-    for (int size = 2; size <= 64; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        const uint64_t ok = shfl_xor_u64(mk, stride);
-        const int32_t oi = __shfl_xor(mi, stride);
-        const int32_t op = __shfl_xor(mp, stride);
-        const bool up = (lane & size) == 0;
-        const bool lower = (lane & stride) == 0;
-        const bool olt = pair_lt(ok, oi, mk, mi);
-        const bool ogt = pair_lt(mk, mi, ok, oi);
-        const bool take = (lower == up) ? olt : ogt;
-        mk = take ? ok : mk;
-        mi = take ? oi : mi;
-        mp = take ? op : mp;
+      const double rad = support_r_h * cd.h;
+      const double rad2 = rad * rad;
+      const bool valid = lane < ntop;
+      const uint32_t m = popc(__ballot(valid && bitsd(s.key[0]) <= rad2));
+      if (lane < k) nbr[p * k + lane] = valid ? s.pos[0] : 0;
+      if (lane == 0) support[p] = (uint8_t)((finite && ntop == k) ? m : 0);
+      if (out_nbr || out_keys) {
+        // ascending (key, index) order for the caller: bitonic sort across lanes
+        uint64_t mk = valid ? s.key[0] : kEmptyKey;
+        int32_t mi = valid ? s.idx[0] : 0x7fffffff;
+        for (int size = 2; size <= 64; size <<= 1) {
+          for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t ok = shfl_xor_u64(mk, stride);
+            const int32_t oi = __shfl_xor(mi, stride);
+            const bool up = (lane & size) == 0;
+            const bool lower = (lane & stride) == 0;
+            const bool olt = pair_lt(ok, oi, mk, mi);
+            const bool ogt = pair_lt(mk, mi, ok, oi);
+            const bool take = (lower == up) ? olt : ogt;
+            mk = take ? ok : mk;
+            mi = take ? oi : mi;
+          }
+        }
+        if (lane < k) {
+          if (out_nbr) out_nbr[qi * k + lane] = valid ? mi : -1;
+          if (out_keys) out_keys[qi * k + lane] = valid ? bitsd(mk) : bitsd(0x7ff8000000000000ull);
+        }
       }
     }
-    const double rad = support_r_h * cd.h;
-    const double rad2 = rad * rad;
-    const bool valid = lane < ntop;
-    const uint32_t m = popc(__ballot(valid && __longlong_as_double((long long)mk) <= rad2));
-    if (lane < k) {
-      nbr[p * k + lane] = valid ? mp : 0;
-      if (out_nbr) out_nbr[qi * k + lane] = valid ? mi : -1;
-      if (out_keys)
-        out_keys[qi * k + lane] = valid ? __longlong_as_double((long long)mk)
-                                        : __longlong_as_double(0x7ff8000000000000ll);
-    }
-    if (lane == 0) support[p] = (uint8_t)((finite && ntop == k) ? m : 0);
   }
 }
 
@@ -399,7 +740,8 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, double 
                       int32_t *nbr, uint8_t *support, int32_t *out_nbr, double *out_keys,
                       hipStream_t s) {
   if (qv.n == 0) return hipSuccess;
-  int64_t blocks = (qv.n + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t tasks = (qv.n + kChunk - 1) / kChunk;
+  int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_knn, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g, qv, k,
                      support_r_h, nbr, support, out_nbr, out_keys);

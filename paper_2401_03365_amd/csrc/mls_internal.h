@@ -11,6 +11,8 @@ namespace mls {
 
 constexpr int kWave = 64;
 constexpr uint64_t kEmptyKey = ~0ull;  // hash slot marker and non-finite point key
+constexpr int kMaxLevels = 8;           // grid levels: cell edges c, 2c, ..., 128c
+constexpr int kLevelShift = 60;         // hash keys carry the level in bits 60..62
 
 // Per-cloud geometry and parameters, resident in device memory.
 struct CloudDev {
@@ -30,12 +32,14 @@ struct CloudDev {
 struct GridView {
   const float4 *pts;         // sorted points, w = original index bits
   const int32_t *inv_perm;   // original index -> sorted position
-  const uint4 *table;        // hash slots: {key lo, key hi, start, count}
+  const uint4 *table;        // hash slots: {key lo, key hi, start, count}, all levels
   const CloudDev *clouds;    // n_clouds entries
   uint64_t hash_mask;        // capacity - 1
   int32_t n_clouds;
-  int32_t morton_bits;       // bits per axis in the key (same for all clouds)
+  int32_t morton_bits;       // bits per axis of the level-0 key (same for all clouds)
   int64_t n_points;
+  int32_t n_levels;          // levels present in the hash (1..kMaxLevels)
+  int32_t hash_shift;        // 64 - log2(capacity)
 };
 
 // Host-side handle contents.
@@ -76,19 +80,27 @@ __device__ __forceinline__ uint64_t cell_key(int32_t cloud, int32_t ix, int32_t 
   return ((uint64_t)cloud << (3 * bits)) | m;
 }
 
-__device__ __forceinline__ uint64_t hash64(uint64_t x) {
-  // splitmix64 finaliser
-  x ^= x >> 30;
-  x *= 0xbf58476d1ce4e5b9ull;
-  x ^= x >> 27;
-  x *= 0x94d049bb133111ebull;
-  x ^= x >> 31;
-  return x;
+// Hash key of the level-`level` cell (ix, iy, iz) (coordinates at that
+// level): the level-0 key shifted right by 3*level -- a level-l cell is a
+// contiguous range of the Morton-sorted points -- tagged with the level.
+__device__ __forceinline__ uint64_t level_cell_key(int32_t cloud, int32_t ix, int32_t iy,
+                                                   int32_t iz, int32_t bits, int level) {
+  return cell_key(cloud, ix, iy, iz, bits - level) | ((uint64_t)level << kLevelShift);
+}
+
+__device__ __forceinline__ uint64_t level_key(uint64_t key0, int level) {
+  return (key0 >> (3 * level)) | ((uint64_t)level << kLevelShift);
+}
+
+// Multiplicative (Fibonacci) hash: the high bits of key * 2^64/phi select
+// the slot of a table of 2^(64 - shift) slots.
+__device__ __forceinline__ uint64_t hash_slot(uint64_t key, int shift) {
+  return (key * 0x9e3779b97f4a7c15ull) >> shift;
 }
 
 // Returns {start, count} of the cell, count 0 if the cell is empty.
 __device__ __forceinline__ int2 lookup_cell(const GridView &g, uint64_t key) {
-  uint64_t slot = hash64(key) & g.hash_mask;
+  uint64_t slot = hash_slot(key, g.hash_shift);
   for (uint64_t probe = 0; probe <= g.hash_mask; ++probe) {
     uint4 e = g.table[slot];
     uint64_t k = (uint64_t)e.x | ((uint64_t)e.y << 32);
@@ -125,10 +137,10 @@ hipError_t radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, i
                             hipStream_t s);
 hipError_t launch_gather(const float *pts, const int32_t *vals, int64_t n, float4 *sorted,
                          int32_t *inv_perm, hipStream_t s);
-hipError_t launch_count_cells(const uint64_t *keys, int64_t n, unsigned long long *count,
-                              hipStream_t s);
-hipError_t launch_build_table(const uint64_t *keys, int64_t n, uint4 *table, uint64_t capacity,
-                              hipStream_t s);
+hipError_t launch_count_cells(const uint64_t *keys, int64_t n, int n_levels,
+                              unsigned long long *counts, hipStream_t s);
+hipError_t launch_build_table(const uint64_t *keys, int64_t n, int n_levels, uint4 *table,
+                              uint64_t capacity, hipStream_t s);
 
 struct QueryView {
   const void *q;            // queries, n x 3

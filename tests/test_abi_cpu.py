@@ -98,7 +98,7 @@ def test_build_grid_rejects_bad_arguments_on_host(lib):
 def test_project_rejects_bad_arguments_on_host(lib):
     from paper_2401_03365_amd import _abi
     fake = ctypes.c_void_p(0x100000)
-    prm = _abi.MlsParams(k=8, precision=0, support_radius_h=3.0, min_support=3, reserved=0)
+    prm = _abi.MlsParams(k=8, precision=0, support_radius_h=3.0, min_support=3, stages=0)
     # null grid
     assert lib.mls_project(None, ctypes.byref(prm), fake, 0, 10, None, fake, fake, None, fake,
                            1 << 20, None) == _abi.MLS_ERR_INVALID_ARGUMENT
