@@ -71,7 +71,8 @@ ProjLayout proj_layout(int32_t n_clouds, int32_t k, int64_t n) {
   ProjLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
-  L.nbr = take(4 * (size_t)n * (size_t)k);
+  // neighbour lists in tiles of 64 queries (the last tile padded)
+  L.nbr = take(4 * (size_t)((n + 63) / 64) * 64 * (size_t)k);
   L.support = take((size_t)n);
   L.qcloud = take(n_clouds > 1 ? 4 * (size_t)n : 0);
   L.offsets = take(8 * ((size_t)n_clouds + 1));

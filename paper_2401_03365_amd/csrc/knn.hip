@@ -694,7 +694,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       const double rad2 = rad * rad;
       const bool valid = lane < ntop;
       const uint32_t m = popc(__ballot(valid && bitsd(s.key[0]) <= rad2));
-      if (lane < k) nbr[p * k + lane] = valid ? s.pos[0] : 0;
+      // lists are stored per tile of 64 consecutive queries, neighbour-major:
+      // entry j of query p at [(p / 64) * 64 k + j * 64 + p % 64]
+      if (lane < k) nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = valid ? s.pos[0] : 0;
       if (lane == 0) support[p] = (uint8_t)((finite && ntop == k) ? m : 0);
       if (out_nbr || out_keys) {
         // ascending (key, index) order for the caller: bitonic sort across lanes

@@ -103,6 +103,19 @@ __device__ __forceinline__ int64_t clamp_pos(int32_t v, int64_t n) {
   return (v >= 0 && (int64_t)v < n) ? v : 0;
 }
 
+constexpr int kBatch = kChunk;  // neighbour coordinates fetched together
+
+// Issues the loads of neighbours j0 .. j0 + kBatch - 1 (fewer at the end of
+// the list) before any of them is used, so their latencies overlap.
+__device__ __forceinline__ void load_batch(const GridView &g, const int32_t *nb, int j0, int k,
+                                           float4 PB[kBatch]) {
+  int32_t id[kBatch];
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b) id[b] = (j0 + b < k) ? nb[(j0 + b) * 64] : 0;
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b) PB[b] = g.pts[clamp_pos(id[b], g.n_points)];
+}
+
 template <bool kF32>
 __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv, int32_t k,
                                                         int32_t min_support,
@@ -133,7 +146,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
   const int cloud = qv.qcloud ? qv.qcloud[qi] : 0;
   const double h = g.clouds[cloud].h;
   const double ih = 1.0 / h;
-  const int32_t *nb = nbr + p * k;
+  // neighbour j of query p: nb[j * 64] (tile layout of the search kernel)
+  const int32_t *nb = nbr + (p >> 6) * 64 * k + (p & 63);
 
   // ---- pass 1 -------------------------------------------------------------
   double S0, S1[3], S2[6];
@@ -141,8 +155,13 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     S0 = 0.0;
     for (int a = 0; a < 3; ++a) S1[a] = 0.0;
     for (int a = 0; a < 6; ++a) S2[a] = 0.0;
-    for (int j = 0; j < k; ++j) {
-      const float4 P = g.pts[clamp_pos(nb[j], g.n_points)];
+    for (int j0 = 0; j0 < k; j0 += kBatch) {
+      float4 PB[kBatch];
+      load_batch(g, nb, j0, k, PB);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+      if (j0 + b >= k) break;
+      const float4 P = PB[b];
       const double dx = ((double)P.x - r[0]) * ih;
       const double dy = ((double)P.y - r[1]) * ih;
       const double dz = ((double)P.z - r[2]) * ih;
@@ -152,6 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
       S1[0] += wx; S1[1] += wy; S1[2] += wz;
       S2[0] += wx * dx; S2[1] += wx * dy; S2[2] += wx * dz;
       S2[3] += wy * dy; S2[4] += wy * dz; S2[5] += wz * dz;
+      }
     }
   } else {
     const float rx = (float)r[0], ry = (float)r[1], rz = (float)r[2];
@@ -162,9 +182,12 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     CompSum<10> A;
     A.zero();
     for (int j0 = 0; j0 < k; j0 += kChunk) {
-      const int je = min(k, j0 + kChunk);
-      for (int j = j0; j < je; ++j) {
-        const float4 P = g.pts[clamp_pos(nb[j], g.n_points)];
+      float4 PB[kBatch];
+      load_batch(g, nb, j0, k, PB);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (j0 + b >= k) break;
+        const float4 P = PB[b];
         const float dx = ((P.x - rx) - ex) * ihf;
         const float dy = ((P.y - ry) - ey) * ihf;
         const float dz = ((P.z - rz) - ez) * ihf;
@@ -190,8 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     for (int i = 0; i < 15; ++i) qs.s[i] = 0.0;
     for (int i = 0; i < 6; ++i) qs.b[i] = 0.0;
     const double tn0 = pf.t * pf.n[0], tn1 = pf.t * pf.n[1], tn2 = pf.t * pf.n[2];
-    for (int j = 0; j < k; ++j) {
-      const float4 P = g.pts[clamp_pos(nb[j], g.n_points)];
+    for (int j0 = 0; j0 < k; j0 += kBatch) {
+      float4 PB[kBatch];
+      load_batch(g, nb, j0, k, PB);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+      if (j0 + b >= k) break;
+      const float4 P = PB[b];
       const double e0 = ((double)P.x - r[0]) * ih - tn0;
       const double e1 = ((double)P.y - r[1]) * ih - tn1;
       const double e2 = ((double)P.z - r[2]) * ih - tn2;
@@ -208,6 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
       qs.s[13] += wyy * xy; qs.s[14] += wyy * yy;
       qs.b[0] += w * f; qs.b[1] += wx * f; qs.b[2] += wy * f;
       qs.b[3] += wxx * f; qs.b[4] += wxy * f; qs.b[5] += wyy * f;
+      }
     }
   } else {
     const float rx = (float)r[0], ry = (float)r[1], rz = (float)r[2];
@@ -222,9 +251,12 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     CompSum<21> A;
     A.zero();
     for (int j0 = 0; j0 < k; j0 += kChunk) {
-      const int je = min(k, j0 + kChunk);
-      for (int j = j0; j < je; ++j) {
-        const float4 P = g.pts[clamp_pos(nb[j], g.n_points)];
+      float4 PB[kBatch];
+      load_batch(g, nb, j0, k, PB);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (j0 + b >= k) break;
+        const float4 P = PB[b];
         const float e0 = ((P.x - rx) - ex) * ihf - tn0;
         const float e1 = ((P.y - ry) - ey) * ihf - tn1;
         const float e2 = ((P.z - rz) - ez) * ihf - tn2;
