@@ -180,8 +180,8 @@ mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
  * query i belongs to the cloud of point i) or, for one cloud, that every
  * query belongs to it.
  *
- * Bytes of device workspace mls_project / mls_knn / mls_project_backward
- * need for n_queries queries with k neighbours (host). */
+ * Bytes of device workspace mls_project / mls_knn need for n_queries
+ * queries with k neighbours (host). */
 size_t mls_project_workspace_bytes(const mls_grid *grid, int32_t k,
                                    int64_t n_queries);
 
@@ -212,18 +212,44 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params,
                        uint8_t *out_status, int32_t *out_neighbors,
                        void *workspace, size_t workspace_bytes, void *stream);
 
-/* Adjoint of mls_project with respect to the query and point positions, with
- * the neighbour lists and statuses of the forward pass held fixed and every
- * per-query moment recomputed.
- *   neighbors      n_queries x k lists from mls_project (ORIGINAL indices),
- *                  or NULL to recompute them bit-exactly.
- *   grad_out       n_queries x 3 in `dtype`: dL/d out.
- *   grad_queries   n_queries x 3 in `dtype`, overwritten with dL/d r.
- *   grad_points    n_points x 3 FP32 or FP64 (`dtype`), overwritten with
- *                  dL/d p (sum over every query that has the point in its
- *                  list).
- * When the queries are the cloud's own points, the gradient with respect to
- * the cloud is grad_queries + grad_points. */
+/* Bytes of device workspace mls_project_backward needs: the projection's
+ * workspace plus a sorted-order accumulation buffer of 3 values per cloud
+ * point (FP32 for MLS_PREC_FP32_MOMENTS, FP64 for MLS_PREC_FP64) (host).
+ * Returns 0 for invalid arguments. */
+size_t mls_project_backward_workspace_bytes(const mls_grid *grid, int32_t k,
+                                            int64_t n_queries, int32_t precision);
+
+/* Adjoint (vector-Jacobian product) of one mls_project pass with respect to
+ * the query and point positions. Not in the paper, which has no derivative:
+ * it is the reverse-mode derivative of the projection of Section 1.4, Eq.
+ * (1.1) and Section 2.1 (plane by weighted covariance, quadratic height fit,
+ * out = q + h a_0 n) with the neighbour lists and the statuses held fixed and
+ * every per-query moment recomputed with the forward's own arithmetic
+ * (params->precision). The derivative of the unit normal is that of the
+ * simple smallest eigenvalue; where that eigenvalue is exactly repeated the
+ * normal's contribution is dropped (those queries carry
+ * MLS_PT_FLAG_NORMAL_AMBIGUOUS in the forward).
+ *   queries        as in mls_project (same dtype, count, offsets).
+ *   neighbors      device, nullable: n_queries x k ORIGINAL indices as
+ *                  written by mls_project / mls_knn. An entry outside
+ *                  [0, n_points) makes its query an outlier. NULL recomputes
+ *                  the lists with the search of mls_project (bit-identical).
+ *   grad_out       device, n_queries x 3 in `dtype`: dL/d out.
+ *   grad_queries   device, n_queries x 3 in `dtype`, overwritten with dL/d r
+ *                  (OUTLIER: grad_out; NONFINITE query: 0).
+ *   grad_points    device, n_points x 3 in `dtype`, overwritten with dL/d p
+ *                  for every point of the grid (sum over the queries whose
+ *                  list holds the point; 0 for the others). Must be device
+ *                  memory from hipMalloc (hardware float atomics).
+ *   workspace      device, at least mls_project_backward_workspace_bytes,
+ *                  256-byte aligned; required even when n_queries is 0.
+ * The summation order of the point gradients follows the hardware order of
+ * atomic additions, so they can differ between runs in the last bits; the
+ * query gradients are deterministic. Errors: MLS_ERR_INVALID_ARGUMENT for
+ * null or inconsistent arguments, MLS_ERR_WORKSPACE_TOO_SMALL,
+ * MLS_ERR_TOO_FEW_POINTS as in mls_project, MLS_ERR_HIP for a failed launch.
+ * When the queries are the cloud's own points (the usual first pass), the
+ * gradient with respect to the cloud is grad_queries + grad_points. */
 mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
                                 const void *queries, mls_dtype dtype,
                                 int64_t n_queries, const int64_t *query_offsets,

@@ -167,19 +167,31 @@ class Grid:
     def project_backward(self, queries: torch.Tensor, grad_out: torch.Tensor, k: int,
                          precision: str = "fp32", neighbors: Optional[torch.Tensor] = None,
                          query_offsets=None, support_radius_h: float = 3.0, min_support: int = 3):
-        """Adjoint of one pass: returns (grad_queries, grad_points)."""
+        """Adjoint of one pass with lists and statuses fixed: returns
+        (grad_queries, grad_points), both in the queries' dtype.
+        ``neighbors``: the (n, k) int32 original-index lists of the forward
+        pass, or None to recompute them."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
         params = self._params(k, precision, support_radius_h, min_support)
-        grad_out = grad_out.contiguous().to(queries.dtype)
+        lib = _abi.load()
+        if grad_out.shape != queries.shape:
+            raise ValueError("grad_out must have the shape of queries")
+        grad_out = grad_out.to(device=self.device, dtype=queries.dtype).contiguous()
+        if neighbors is not None:
+            if neighbors.shape != (n, k) or neighbors.dtype != torch.int32 or not neighbors.is_cuda:
+                raise ValueError("neighbors must be a CUDA (n, k) int32 tensor")
+            neighbors = neighbors.contiguous()
         gq = torch.empty_like(queries)
         gp = torch.empty((self.n_points, 3), dtype=queries.dtype, device=self.device)
-        ws = self._proj_workspace(k, n)
+        nbytes = lib.mls_project_backward_workspace_bytes(self._handle, k, n, params.precision)
+        if nbytes == 0:
+            raise ValueError("invalid k or query count")
+        ws = _workspace(nbytes, self.device)
         qo, qo_p = _host_i64(query_offsets)
-        code = _abi.load().mls_project_backward(
+        code = lib.mls_project_backward(
             self._handle, ctypes.byref(params), _ptr(queries), _dtype_code(queries), n, qo_p,
-            _ptr(neighbors.contiguous() if neighbors is not None else None), _ptr(grad_out),
-            _ptr(gq), _ptr(gp), _ptr(ws), ws.numel(), _stream())
+            _ptr(neighbors), _ptr(grad_out), _ptr(gq), _ptr(gp), _ptr(ws), ws.numel(), _stream())
         _abi.check(code, "mls_project_backward")
         return gq, gp
 
@@ -225,6 +237,7 @@ class MLSProject(torch.autograd.Function):
         out, status, nbr = grid.project(queries.detach().contiguous(), k, precision,
                                         return_neighbors=True)
         ctx.grid, ctx.k, ctx.precision = grid, k, precision
+        ctx.points_dtype = points.dtype
         ctx.save_for_backward(queries.detach(), nbr)
         ctx.mark_non_differentiable(status)
         return out, status
@@ -233,7 +246,7 @@ class MLSProject(torch.autograd.Function):
     def backward(ctx, grad_out, grad_status):
         queries, nbr = ctx.saved_tensors
         gq, gp = ctx.grid.project_backward(queries, grad_out, ctx.k, ctx.precision, neighbors=nbr)
-        return gq, gp.to(queries.dtype), None, None, None
+        return gq, gp.to(ctx.points_dtype), None, None, None
 
 
 def mls_project(queries, points, grid: Grid, k: int, precision: str = "fp32"):

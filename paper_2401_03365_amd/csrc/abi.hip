@@ -80,6 +80,18 @@ ProjLayout proj_layout(int32_t n_clouds, int32_t k, int64_t n) {
   return L;
 }
 
+// The adjoint's workspace: the projection layout, then the sorted-order
+// accumulation buffer of the point gradients (3 per point, in the type of the
+// per-neighbour arithmetic).
+size_t bwd_gp_offset(int32_t n_clouds, int32_t k, int64_t n) {
+  return proj_layout(n_clouds, k, n).total;
+}
+
+size_t bwd_total(int32_t n_clouds, int32_t k, int64_t n, int64_t n_points, int32_t precision) {
+  const size_t elem = precision == MLS_PREC_FP32_MOMENTS ? 4 : 8;
+  return bwd_gp_offset(n_clouds, k, n) + align256(3 * elem * (size_t)n_points);
+}
+
 bool offsets_ok(const int64_t *off, int32_t c, int64_t n) {
   if (off[0] != 0 || off[c] != n) return false;
   for (int32_t i = 0; i < c; ++i)
@@ -354,6 +366,13 @@ size_t mls_project_workspace_bytes(const mls_grid *grid, int32_t k, int64_t n_qu
   return proj_layout(grid->g.n_clouds, k, n_queries).total;
 }
 
+size_t mls_project_backward_workspace_bytes(const mls_grid *grid, int32_t k, int64_t n_queries,
+                                            int32_t precision) {
+  if (!grid || k < 1 || k > MLS_MAX_K || n_queries < 0) return 0;
+  if (precision != MLS_PREC_FP64 && precision != MLS_PREC_FP32_MOMENTS) return 0;
+  return bwd_total(grid->g.n_clouds, k, n_queries, grid->g.n_points, precision);
+}
+
 }  // extern "C"
 
 namespace {
@@ -456,11 +475,41 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
                                 const int64_t *query_offsets, const int32_t *neighbors,
                                 const void *grad_out, void *grad_queries, void *grad_points,
                                 void *workspace, size_t workspace_bytes, void *stream) {
-  (void)queries; (void)dtype; (void)n_queries; (void)query_offsets;
-  (void)neighbors; (void)grad_out; (void)grad_queries; (void)grad_points; (void)workspace;
-  (void)workspace_bytes; (void)stream;
-  if (!grid || !params) return MLS_ERR_INVALID_ARGUMENT;
-  return MLS_ERR_UNSUPPORTED;
+  g_last_error[0] = 0;
+  if (!params || !grid) return MLS_ERR_INVALID_ARGUMENT;
+  if (params->precision != MLS_PREC_FP64 && params->precision != MLS_PREC_FP32_MOMENTS)
+    return MLS_ERR_INVALID_ARGUMENT;
+  if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
+      params->min_support < 0)
+    return MLS_ERR_INVALID_ARGUMENT;
+  if (n_queries > 0 && (!grad_out || !grad_queries)) return MLS_ERR_INVALID_ARGUMENT;
+  // the point gradients are accumulated in the workspace even without queries
+  if (!grad_points || !workspace) return MLS_ERR_INVALID_ARGUMENT;
+  if (params->k >= 1 && params->k <= MLS_MAX_K && n_queries >= 0 &&
+      workspace_bytes < bwd_total(grid->g.n_clouds, params->k, n_queries, grid->g.n_points,
+                                  params->precision))
+    return MLS_ERR_WORKSPACE_TOO_SMALL;
+  hipStream_t s = (hipStream_t)stream;
+  mls::QueryView qv;
+  ProjLayout L;
+  mls_status st = prepare_queries(grid, params->k, queries, dtype, n_queries, query_offsets,
+                                  workspace, workspace_bytes, s, &qv, &L);
+  if (st != MLS_OK) return st;
+  if (((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
+  char *ws = (char *)workspace;
+  int32_t *nbr = (int32_t *)(ws + L.nbr);
+  if (n_queries > 0) {
+    if (neighbors)
+      MLS_HIP(mls::launch_lists_from_caller(grid->g.view, qv, params->k, neighbors, nbr, s));
+    else
+      MLS_HIP(mls::launch_knn(grid->g.view, qv, params->k, params->support_radius_h, nbr,
+                              (uint8_t *)(ws + L.support), nullptr, nullptr, s));
+  }
+  void *gp = ws + bwd_gp_offset(grid->g.n_clouds, params->k, n_queries);
+  MLS_HIP(mls::launch_mls_backward(grid->g.view, qv, params->k, params->precision,
+                                   params->support_radius_h, params->min_support, nbr, grad_out,
+                                   grad_queries, gp, grad_points, s));
+  return MLS_OK;
 }
 
 }  // extern "C"

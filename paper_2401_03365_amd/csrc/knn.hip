@@ -59,19 +59,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Canonical squared distance: sub, mul, mul, mul, add, add, no contraction.
-__device__ __forceinline__ double canon_key(double px, double py, double pz, double rx,
-                                            double ry, double rz) {
-#pragma clang fp contract(off)
-  const double dx = px - rx;
-  const double dy = py - ry;
-  const double dz = pz - rz;
-  const double sx = dx * dx;
-  const double sy = dy * dy;
-  const double sz = dz * dz;
-  return (sx + sy) + sz;
-}
-
 __device__ __forceinline__ uint64_t dbits(double d) { return (uint64_t)__double_as_longlong(d); }
 __device__ __forceinline__ double bitsd(uint64_t b) { return __longlong_as_double((long long)b); }
 

@@ -28,6 +28,19 @@ struct CloudDev {
   int64_t send;
 };
 
+// Canonical squared distance: sub, mul, mul, mul, add, add, no contraction.
+__device__ __forceinline__ double canon_key(double px, double py, double pz, double rx,
+                                            double ry, double rz) {
+#pragma clang fp contract(off)
+  const double dx = px - rx;
+  const double dy = py - ry;
+  const double dz = pz - rz;
+  const double sx = dx * dx;
+  const double sy = dy * dy;
+  const double sz = dz * dz;
+  return (sx + sy) + sz;
+}
+
 // Device-resident view of a built grid, passed to kernels by value.
 struct GridView {
   const float4 *pts;         // sorted points, w = original index bits
@@ -157,6 +170,12 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, double 
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               int32_t precision, int32_t min_support, const int32_t *nbr_tiles,
                               const uint8_t *support, void *out, uint8_t *status, hipStream_t s);
+hipError_t launch_lists_from_caller(const GridView &g, const QueryView &qv, int32_t k,
+                                    const int32_t *user, int32_t *nbr_tiles, hipStream_t s);
+hipError_t launch_mls_backward(const GridView &g, const QueryView &qv, int32_t k,
+                               int32_t precision, double support_radius_h, int32_t min_support,
+                               const int32_t *nbr_tiles, const void *grad_out, void *grad_q,
+                               void *gp_sorted, void *grad_points, hipStream_t s);
 hipError_t launch_fill_cloud_ids(const int64_t *offsets_dev, int32_t n_clouds, int64_t n,
                                  int32_t *qcloud, hipStream_t s);
 }  // namespace mls

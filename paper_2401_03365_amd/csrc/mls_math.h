@@ -183,52 +183,68 @@ __device__ __forceinline__ int quad_index(int i, int j) {
   return base[d] + b;              // within degree ordered by the power of y
 }
 
-// Cholesky of M with the pivot rule of the method: every pivot L_jj^2 must
-// exceed tol * max_j M_jj. On success writes a = M^-1 b and returns true.
-__device__ inline bool quad_solve(const QuadSums &q, double tol, double a[6]) {
-  double M[6][6];
+// Cholesky factor M = L L^T of the quadratic fit's normal matrix, with the
+// pivot rule of the method: every pivot L_jj^2 must exceed tol * max_j M_jj
+// (ok is false otherwise).
+struct Chol6 {
+  double L[6][6];  // lower triangle below the diagonal
+  double inv[6];   // 1 / L_jj
+  bool ok;
+
+  __device__ inline void factor(const QuadSums &q, double tol) {
+    double M[6][6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) M[i][j] = q.s[quad_index(i, j)];
-  double maxdiag = 0.0;
+      for (int j = 0; j < 6; ++j) M[i][j] = q.s[quad_index(i, j)];
+    double maxdiag = 0.0;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) maxdiag = fmax(maxdiag, M[i][i]);
-  double Lm[6][6];
-  double inv[6];
-  bool ok = true;
+    for (int i = 0; i < 6; ++i) maxdiag = fmax(maxdiag, M[i][i]);
+    ok = true;
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    double s = M[j][j];
+    for (int j = 0; j < 6; ++j) {
+      double s = M[j][j];
 #pragma unroll
-    for (int c = 0; c < j; ++c) s -= Lm[j][c] * Lm[j][c];
-    ok = ok && (s > tol * maxdiag);
-    const double d = sqrt(fmax(s, 1e-300));
-    inv[j] = 1.0 / d;
+      for (int c = 0; c < j; ++c) s -= L[j][c] * L[j][c];
+      ok = ok && (s > tol * maxdiag);
+      const double d = sqrt(fmax(s, 1e-300));
+      inv[j] = 1.0 / d;
 #pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
-      double z = M[i][j];
+      for (int i = j + 1; i < 6; ++i) {
+        double z = M[i][j];
 #pragma unroll
-      for (int c = 0; c < j; ++c) z -= Lm[i][c] * Lm[j][c];
-      Lm[i][j] = z * inv[j];
+        for (int c = 0; c < j; ++c) z -= L[i][c] * L[j][c];
+        L[i][j] = z * inv[j];
+      }
     }
   }
-  double y[6];
+
+  // x = M^-1 rhs by forward and back substitution.
+  __device__ inline void solve(const double rhs[6], double x[6]) const {
+    double y[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double z = q.b[i];
+    for (int i = 0; i < 6; ++i) {
+      double z = rhs[i];
 #pragma unroll
-    for (int c = 0; c < i; ++c) z -= Lm[i][c] * y[c];
-    y[i] = z * inv[i];
+      for (int c = 0; c < i; ++c) z -= L[i][c] * y[c];
+      y[i] = z * inv[i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+      double z = y[i];
+#pragma unroll
+      for (int c = i + 1; c < 6; ++c) z -= L[c][i] * x[c];
+      x[i] = z * inv[i];
+    }
   }
-#pragma unroll
-  for (int i = 5; i >= 0; --i) {
-    double z = y[i];
-#pragma unroll
-    for (int c = i + 1; c < 6; ++c) z -= Lm[c][i] * a[c];
-    a[i] = z * inv[i];
-  }
-  return ok;
+};
+
+// Solves the quadratic fit; on success writes a = M^-1 b and returns true.
+__device__ inline bool quad_solve(const QuadSums &q, double tol, double a[6]) {
+  Chol6 ch;
+  ch.factor(q, tol);
+  ch.solve(q.b, a);
+  return ch.ok;
 }
 
 }  // namespace mls

@@ -1,0 +1,190 @@
+"""GPU parity of the adjoint kernel (mls_project_backward) against the
+oracle's finite-difference adjoint with the same fixed lists.
+
+Bar: ||g_gpu - g_fd||_2 / ||g_fd||_2 <= 1e-4 over the checked queries for
+the FP32-moment path (and 1e-6 for the FP64 path), separately for the query
+gradients and the point gradients; queries whose normal is flagged ambiguous
+are left out of the subset. Also: the plane closed form, the rigid-motion
+invariants at a larger size, the trivial statuses, lists passed vs
+recomputed, and the autograd wrapper."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_03365_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"fp64": 1e-6, "fp32": 1e-4}
+
+
+def api():
+    from paper_2401_03365_amd import api as a
+    return a
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def gpu_backward(P32, Q, k, h, precision, gout, nbr=None, cell_size=None):
+    a = api()
+    Pt = torch.from_numpy(np.ascontiguousarray(P32, dtype=np.float32)).cuda()
+    Qt = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    g = a.Grid(Pt, h, cell_size=cell_size)
+    nb = torch.from_numpy(np.ascontiguousarray(nbr, dtype=np.int32)).cuda() if nbr is not None else None
+    gq, gp = g.project_backward(Qt, torch.from_numpy(np.ascontiguousarray(gout)).cuda().to(Qt.dtype),
+                                k, precision, neighbors=nb)
+    torch.cuda.synchronize()
+    return gq.cpu().numpy().astype(np.float64), gp.cpu().numpy().astype(np.float64)
+
+
+def fd_case(orc, P32, Q, k, h, seed):
+    P = P32.astype(np.float64)
+    nbr, _ = orc.knn(P, Q, k)
+    _, st = orc.project(P, Q, k, h, nbr=nbr)
+    keep = (st & 0x10) == 0
+    Q, nbr = Q[keep], nbr[keep]
+    gout = np.random.default_rng(seed).normal(size=Q.shape)
+    gq, gp = orc.grad_fd(P, Q, k, h, nbr, gout)
+    return Q, nbr, gout, gq, gp
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("lists", ["given", "recomputed"])
+def test_sphere_vs_fd(orc, precision, lists):
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    rng = np.random.default_rng(3)
+    Q = P[rng.choice(P.shape[0], 400, replace=False)].astype(np.float64)
+    Q, nbr, gout, fq, fp = fd_case(orc, P, Q, 32, h, 4)
+    gq, gp = gpu_backward(P, Q, 32, h, precision, gout, nbr if lists == "given" else None)
+    assert rel(gq, fq) <= BAR[precision], rel(gq, fq)
+    assert rel(gp, fp) <= BAR[precision], rel(gp, fp)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_off_surface_queries_vs_fd(orc, precision):
+    # queries up to 1.5 h off a noisy torus, k = 48 (several 8-neighbour
+    # batches and a ragged tail of the 64-query tile)
+    P = synth.torus(30000, sigma=0.005, seed=2)
+    h = synth.mean_nn_h(P)
+    rng = np.random.default_rng(5)
+    Q = P[rng.choice(P.shape[0], 301, replace=False)].astype(np.float64)
+    Q = Q + rng.uniform(-1.5, 1.5, Q.shape) * h
+    Q, nbr, gout, fq, fp = fd_case(orc, P, Q, 48, h, 6)
+    gq, gp = gpu_backward(P, Q, 48, h, precision, gout, nbr)
+    assert rel(gq, fq) <= BAR[precision], rel(gq, fq)
+    assert rel(gp, fp) <= BAR[precision], rel(gp, fp)
+
+
+def test_plane_only_queries_vs_fd(orc):
+    # support of 4 or 5 within 3h (fewer than 6): plane-only projection
+    rng = np.random.default_rng(8)
+    xy = rng.uniform(-1, 1, (400, 2))
+    P = np.column_stack([xy, 0.1 * xy[:, 0] ** 2]).astype(np.float32)
+    P = np.vstack([P, np.array([[3.0, 3.0, 0.0], [3.01, 3.0, 0.002], [3.0, 3.012, -0.001],
+                                [3.013, 3.011, 0.001], [3.006, 2.99, 0.0]], np.float32)])
+    h = 0.01
+    Q = P[-5:].astype(np.float64) + 1e-3
+    P64 = P.astype(np.float64)
+    nbr, _ = orc.knn(P64, Q, 8)
+    _, st = orc.project(P64, Q, 8, h, nbr=nbr)
+    assert np.all((st & 0x0F) == 2)
+    gout = rng.normal(size=Q.shape)
+    fq, fp = orc.grad_fd(P64, Q, 8, h, nbr, gout)
+    gq, gp = gpu_backward(P, Q, 8, h, "fp64", gout, nbr)
+    assert rel(gq, fq) <= 1e-6
+    assert rel(gp, fp) <= 1e-6
+
+
+def test_plane_closed_form():
+    rng = np.random.default_rng(21)
+    xy = rng.integers(-64, 65, (4000, 2)) / 64.0
+    P = np.column_stack([xy, 0.25 * xy[:, 0] - 0.5 * xy[:, 1] + 0.125]).astype(np.float32)
+    n = np.array([-0.25, 0.5, 1.0])
+    n /= np.linalg.norm(n)
+    h = synth.mean_nn_h(P)
+    Q = P[:500].astype(np.float64) + rng.uniform(-0.5, 0.5, (500, 1)) * h * n
+    gout = rng.normal(size=Q.shape)
+    for precision, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        gq, _ = gpu_backward(P, Q, 24, h, precision, gout)
+        expect = gout - (gout @ n)[:, None] * n
+        assert np.abs(gq - expect).max() <= tol * np.abs(gout).max(), precision
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rigid_motion_invariants_at_scale(precision):
+    # whole-cloud queries (the aligned slot order), 200k points
+    a = api()
+    P = synth.sh_sphere(200000, seed=4)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    Qt = Pt.double()
+    out, st = g.project(Qt, 32, precision)
+    gout = torch.from_numpy(np.random.default_rng(17).normal(size=P.shape)).cuda()
+    gq, gp = g.project_backward(Qt, gout, 32, precision)
+    torch.cuda.synchronize()
+    ok = ((st & 0x10) == 0).cpu().numpy()
+    assert ok.mean() > 0.99
+    Q, O, G = Qt.cpu().numpy(), out.cpu().numpy(), gout.cpu().numpy()
+    GQ, GP = gq.cpu().numpy(), gp.cpu().numpy()
+    scale = np.abs(G).sum()
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    np.testing.assert_allclose(GQ.sum(0) + GP.sum(0), G.sum(0), atol=tol * scale)
+    lhs = np.cross(Q, GQ).sum(0) + np.cross(P.astype(np.float64), GP).sum(0)
+    np.testing.assert_allclose(lhs, np.cross(O, G).sum(0), atol=tol * scale)
+
+
+def test_statuses_outlier_and_nonfinite():
+    P = synth.sphere(5000, 0.01, seed=9)
+    h = synth.mean_nn_h(P)
+    Q = np.array([[5.0, 5.0, 5.0], [np.nan, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    gout = np.array([[0.3, -0.2, 0.7], [1.0, 1.0, 1.0], [0.5, 0.5, 0.5]])
+    gq, gp = gpu_backward(P, Q, 16, h, "fp64", gout)
+    np.testing.assert_array_equal(gq[0], gout[0])
+    np.testing.assert_array_equal(gq[1], 0.0)
+    assert np.isfinite(gp).all()
+    assert np.count_nonzero(np.abs(gp).sum(1)) <= 16  # only the third query scatters
+
+
+def test_lists_given_vs_recomputed_and_repeatability():
+    a = api()
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    Q = Pt.double()
+    out, st, nbr = g.project(Q, 32, "fp32", return_neighbors=True)
+    gout = torch.ones_like(Q)
+    gq1, gp1 = g.project_backward(Q, gout, 32, "fp32", neighbors=nbr)
+    gq1b, _ = g.project_backward(Q, gout, 32, "fp32", neighbors=nbr)
+    gq2, gp2 = g.project_backward(Q, gout, 32, "fp32")
+    torch.cuda.synchronize()
+    # same lists, same order: the query gradients repeat bit for bit
+    assert torch.equal(gq1, gq1b)
+    # recomputed lists hold the same sets in the search's own order, so the
+    # sums round differently
+    ok = (st & 0x10) == 0
+    assert (gq1 - gq2)[ok].norm() <= 1e-5 * gq1[ok].norm()
+    assert (gp1 - gp2).norm() <= 1e-5 * gp1.norm()
+
+
+def test_autograd_function():
+    a = api()
+    P = synth.sphere(8000, 0.01, seed=3)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    q = Pt.double().requires_grad_(True)
+    pts = Pt.clone().requires_grad_(True)
+    out, st = a.mls_project(q, pts, g, 24, "fp64")
+    loss = ((out.norm(dim=1) - 1.0) ** 2).mean()
+    loss.backward()
+    gout = 2 * (out.detach().norm(dim=1) - 1.0)[:, None] * out.detach() / out.detach().norm(dim=1)[:, None] / out.shape[0]
+    gq, gp = g.project_backward(q.detach(), gout, 24, "fp64")
+    torch.cuda.synchronize()
+    assert q.grad.dtype == torch.float64 and pts.grad.dtype == torch.float32
+    assert torch.allclose(q.grad, gq, rtol=1e-12, atol=1e-15)
+    assert torch.allclose(pts.grad.double(), gp, rtol=1e-6, atol=1e-9)
