@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--c4-n", type=int, default=2_000_000)
     return ap.parse_args()
 
 
@@ -139,6 +141,75 @@ class _Null:
         return False
 
 
+def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label):
+    """fwd (search + fit) and the adjoint of one pass over the whole cloud,
+    queries = the cloud's points, FP32-moment path, FP32 in and out. The grid
+    is built once; the loss gradient is torch code between the two and is
+    timed apart. value = N / (t_fwd + t_bwd)."""
+    pts = torch.from_numpy(P).cuda()
+    timer = Timer(torch)
+    grid = api.Grid(pts, h, cell_size=default_cell_factor(k) * h)
+    out = torch.empty_like(pts)
+    status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
+
+    def step(record):
+        ctx = timer.span if record else (lambda name: _Null())
+        with ctx("fwd_search"):
+            grid.project(pts, k, "fp32", stages=1, out=out, status=status)
+        with ctx("fwd_fit"):
+            grid.project(pts, k, "fp32", stages=2, out=out, status=status)
+        with ctx("loss_grad"):
+            gy = loss_grad(out)
+        with ctx("bwd"):
+            gq, gp = grid.project_backward(pts, gy, k, "fp32", reuse_lists=True)
+        return gq, gp
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        gq, gp = step(True)
+    torch.cuda.synchronize()
+    br = {n: timer.ms(n) for n in ("fwd_search", "fwd_fit", "loss_grad", "bwd")}
+    t = br["fwd_search"] + br["fwd_fit"] + br["bwd"]
+    ok = bool(torch.isfinite(gq).all().item() and torch.isfinite(gp).all().item())
+    log("%s: fwd %.2f + %.2f ms, loss %.2f ms, bwd %.2f ms, finite grads %s" %
+        (label, br["fwd_search"], br["fwd_fit"], br["loss_grad"], br["bwd"], ok))
+    del grid
+    return {"value": P.shape[0] / (t / 1000.0), "unit": "pts/s", "n_points": int(P.shape[0]),
+            "k": k, "h": h, "breakdown_ms": br, "ms_fwd_plus_bwd": t, "grads_finite": ok}
+
+
+def sh_sphere_loss(torch, field, P):
+    """L = mean_j (|y_j| - rho_j)^2, rho_j = 1 + bump at the sample's own
+    direction (evaluated once on the host)."""
+    w = P.astype(np.float64)
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    rho = torch.from_numpy((1.0 + field.bump(w)).astype(np.float32)).cuda()
+
+    def grad(out):
+        y = out.detach().requires_grad_(True)
+        L = ((y.norm(dim=1) - rho) ** 2).mean()
+        return torch.autograd.grad(L, y)[0]
+    return grad
+
+
+def heightfield_loss(torch, field):
+    """L = mean_j (z_j - f(x_j, y_j))^2 with the generating height field."""
+    fr = torch.tensor(field.freq, dtype=torch.float32, device="cuda")
+    ca = torch.tensor(np.cos(field.alpha), dtype=torch.float32, device="cuda")
+    sa = torch.tensor(np.sin(field.alpha), dtype=torch.float32, device="cuda")
+    ph = torch.tensor(field.phase, dtype=torch.float32, device="cuda")
+
+    def grad(out):
+        y = out.detach().requires_grad_(True)
+        arg = 2.0 * np.pi * fr * (y[:, :1] * ca + y[:, 1:2] * sa) + ph
+        f = field.amp * torch.sin(arg).sum(1)
+        L = ((y[:, 2] - f) ** 2).mean()
+        return torch.autograd.grad(L, y)[0]
+    return grad
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -149,7 +220,7 @@ def main():
     from paper_2401_03365_amd import api, synth
 
     t = time.perf_counter()
-    P = synth.heightfield(args.n, sigma=1e-3, seed=3)
+    P, hfield = synth.heightfield(args.n, sigma=1e-3, seed=3, return_field=True)
     h = synth.mean_nn_h(P)
     log("cloud %d pts generated, h = %.6g (%.1f s)" % (args.n, h, time.perf_counter() - t))
     cf = args.cell_factor if args.cell_factor is not None else default_cell_factor(args.k)
@@ -206,6 +277,17 @@ def main():
            ((ms32 - br32["build"]) / 1000.0),
            "fp64_path": fp64,
            "roofline": roof}
+
+    if not args.no_fwd_bwd:
+        fb = {}
+        fb["heightfield_10M_k48"] = fwd_bwd(api, torch, P, h, args.k,
+                                            heightfield_loss(torch, hfield),
+                                            args.steps, args.warmup, "fwd+bwd heightfield")
+        P4, shf = synth.sh_sphere(args.c4_n, sigma=0.005, seed=4, return_field=True)
+        h4 = synth.mean_nn_h(P4)
+        fb["sh_sphere_2M_k32"] = fwd_bwd(api, torch, P4, h4, 32, sh_sphere_loss(torch, shf, P4),
+                                         args.steps, args.warmup, "fwd+bwd sh sphere")
+        res["fwd_bwd"] = fb
 
     if not args.no_cpu_baseline:
         import oracle

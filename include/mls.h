@@ -230,10 +230,16 @@ size_t mls_project_backward_workspace_bytes(const mls_grid *grid, int32_t k,
  * normal's contribution is dropped (those queries carry
  * MLS_PT_FLAG_NORMAL_AMBIGUOUS in the forward).
  *   queries        as in mls_project (same dtype, count, offsets).
+ *   params         as in mls_project; params->stages selects the lists:
+ *                  MLS_STAGE_ALL (0, or SEARCH|FIT): `neighbors` if given,
+ *                  else a fresh search (the lists of mls_project);
+ *                  MLS_STAGE_FIT: the lists that the last search on this same
+ *                  workspace left there (mls_project with the same grid,
+ *                  queries, k and offsets, nothing else run on the workspace
+ *                  since); `neighbors` must then be NULL.
  *   neighbors      device, nullable: n_queries x k ORIGINAL indices as
  *                  written by mls_project / mls_knn. An entry outside
- *                  [0, n_points) makes its query an outlier. NULL recomputes
- *                  the lists with the search of mls_project (bit-identical).
+ *                  [0, n_points) makes its query an outlier.
  *   grad_out       device, n_queries x 3 in `dtype`: dL/d out.
  *   grad_queries   device, n_queries x 3 in `dtype`, overwritten with dL/d r
  *                  (OUTLIER: grad_out; NONFINITE query: 0).

@@ -114,7 +114,12 @@ class Grid:
 
     # ---- workspace --------------------------------------------------------
     def _proj_workspace(self, k: int, n: int) -> torch.Tensor:
-        nbytes = _abi.load().mls_project_workspace_bytes(self._handle, k, n)
+        """One cached workspace for search, fit and adjoint (sized for the
+        adjoint, so that it can reuse the lists of the preceding search)."""
+        lib = _abi.load()
+        nbytes = max(lib.mls_project_workspace_bytes(self._handle, k, n),
+                     lib.mls_project_backward_workspace_bytes(self._handle, k, n,
+                                                              _abi.MLS_PREC_FP64))
         if nbytes == 0:
             raise ValueError("invalid k or query count")
         if self._proj_ws is None or self._proj_ws.numel() < nbytes:
@@ -166,28 +171,31 @@ class Grid:
 
     def project_backward(self, queries: torch.Tensor, grad_out: torch.Tensor, k: int,
                          precision: str = "fp32", neighbors: Optional[torch.Tensor] = None,
-                         query_offsets=None, support_radius_h: float = 3.0, min_support: int = 3):
+                         query_offsets=None, support_radius_h: float = 3.0, min_support: int = 3,
+                         reuse_lists: bool = False):
         """Adjoint of one pass with lists and statuses fixed: returns
         (grad_queries, grad_points), both in the queries' dtype.
         ``neighbors``: the (n, k) int32 original-index lists of the forward
-        pass, or None to recompute them."""
+        pass, or None to recompute them; ``reuse_lists``: take the lists the
+        last search on this grid's workspace left there (the immediately
+        preceding ``project`` of the same queries)."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
-        params = self._params(k, precision, support_radius_h, min_support)
+        stages = _abi.MLS_STAGE_FIT if reuse_lists else 0
+        params = self._params(k, precision, support_radius_h, min_support, stages)
         lib = _abi.load()
         if grad_out.shape != queries.shape:
             raise ValueError("grad_out must have the shape of queries")
         grad_out = grad_out.to(device=self.device, dtype=queries.dtype).contiguous()
         if neighbors is not None:
+            if reuse_lists:
+                raise ValueError("neighbors and reuse_lists exclude each other")
             if neighbors.shape != (n, k) or neighbors.dtype != torch.int32 or not neighbors.is_cuda:
                 raise ValueError("neighbors must be a CUDA (n, k) int32 tensor")
             neighbors = neighbors.contiguous()
         gq = torch.empty_like(queries)
         gp = torch.empty((self.n_points, 3), dtype=queries.dtype, device=self.device)
-        nbytes = lib.mls_project_backward_workspace_bytes(self._handle, k, n, params.precision)
-        if nbytes == 0:
-            raise ValueError("invalid k or query count")
-        ws = _workspace(nbytes, self.device)
+        ws = self._proj_workspace(k, n)
         qo, qo_p = _host_i64(query_offsets)
         code = lib.mls_project_backward(
             self._handle, ctypes.byref(params), _ptr(queries), _dtype_code(queries), n, qo_p,

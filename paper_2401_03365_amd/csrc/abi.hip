@@ -482,6 +482,12 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
       params->min_support < 0)
     return MLS_ERR_INVALID_ARGUMENT;
+  // stages: ALL = lists from `neighbors` or a fresh search; FIT = the lists a
+  // preceding search left in this workspace
+  const bool reuse = params->stages == MLS_STAGE_FIT;
+  if (!(params->stages == MLS_STAGE_ALL || params->stages == (MLS_STAGE_SEARCH | MLS_STAGE_FIT) ||
+        reuse) || (reuse && neighbors))
+    return MLS_ERR_INVALID_ARGUMENT;
   if (n_queries > 0 && (!grad_out || !grad_queries)) return MLS_ERR_INVALID_ARGUMENT;
   // the point gradients are accumulated in the workspace even without queries
   if (!grad_points || !workspace) return MLS_ERR_INVALID_ARGUMENT;
@@ -498,7 +504,7 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   if (((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
-  if (n_queries > 0) {
+  if (n_queries > 0 && !reuse) {
     if (neighbors)
       MLS_HIP(mls::launch_lists_from_caller(grid->g.view, qv, params->k, neighbors, nbr, s));
     else

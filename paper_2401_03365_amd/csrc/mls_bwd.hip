@@ -26,8 +26,8 @@
 //   C, mu -> S0bar, S1bar, S2bar; each neighbour adds
 //     wbar = S0bar + <S1bar, d> + d^T S2bar d,
 //     dbar_i += w (S1bar + 2 S2bar d) - 2 w wbar d.
-// Finally pbar_i = dbar_i / h (scattered with atomics into a sorted-order
-// buffer) and rbar = gbar - sum_i dbar_i / h.
+// Finally pbar_i = dbar_i / h (summed per block in LDS, then added with
+// atomics into a sorted-order buffer) and rbar = gbar - sum_i dbar_i / h.
 //
 // The per-neighbour adjoint runs in the precision of the forward's moments
 // (FP32 with compensated sums, or FP64); the per-query algebra is FP64.
@@ -114,13 +114,61 @@ __device__ __forceinline__ void pass2_adjoint_sums(const GridView &g, const int3
 
 // Second adjoint loop: dbar_i of both passes, pbar_i = dbar_i / h scattered
 // into gp (sorted order, xyz interleaved); returns sum_i dbar_i.
+// Block-level aggregation of the point gradients: an open-addressing table in
+// LDS keyed by sorted position (keys only inserted during the phase; probe
+// step kStride), flushed to the global buffer with one atomic per component and
+// distinct point. The 256 queries of a block are consecutive in Morton order
+// and share most neighbours (about 700 distinct points for 12k list entries
+// at k = 48), so the table removes most global atomics. An entry that finds
+// no slot within kProbes goes straight to global memory.
+template <typename T>
+struct ScatterTable {
+  static constexpr int kLog2 = 11;
+  static constexpr int kSlots = 1 << kLog2;
+  static constexpr int kProbes = 32;
+  static constexpr uint32_t kStride = 523;  // odd: visits every slot
+  int32_t *key;  // kSlots, -1 = empty
+  T *val;        // 3 x kSlots
+  T *gp;         // global, sorted order, xyz interleaved
+
+  __device__ __forceinline__ void add(int32_t pos, T v0, T v1, T v2) const {
+    // positions of a block's neighbours come in runs: the low bits spread a
+    // run over distinct slots, and a collision jumps away from the run
+    uint32_t s = (uint32_t)pos & (kSlots - 1);
+#pragma unroll 1
+    for (int probe = 0; probe < kProbes; ++probe) {
+      int32_t cur = __hip_atomic_load(key + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (cur == -1) {
+        cur = -1;
+        __hip_atomic_compare_exchange_strong(key + s, &cur, pos, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // cur is now the slot's key before the exchange (-1 if ours won)
+        if (cur == -1) cur = pos;
+      }
+      if (cur == pos) {
+        __hip_atomic_fetch_add(val + s, v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(val + kSlots + s, v1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(val + 2 * kSlots + s, v2, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
+      }
+      s = (s + kStride) & (kSlots - 1);
+    }
+    T *dst = gp + 3 * (int64_t)pos;
+    unsafeAtomicAdd(dst + 0, v0);
+    unsafeAtomicAdd(dst + 1, v1);
+    unsafeAtomicAdd(dst + 2, v2);
+  }
+};
+
 template <bool kF32>
 __device__ __forceinline__ void final_adjoint(const GridView &g, const int32_t *nb, int k,
                                               const Rel<kF32> &rel, const FrameT<kF32> &fr,
                                               const Real<kF32> a[6], const Real<kF32> bb[6],
                                               Real<kF32> Sb0, const Real<kF32> Sb1[3],
                                               const Real<kF32> Sb2[6], Real<kF32> ih,
-                                              Real<kF32> *__restrict__ gp, double D[3]) {
+                                              const ScatterTable<Real<kF32>> &tab, double D[3]) {
   using T = Real<kF32>;
   Acc<kF32, 3> A;
   A.zero();
@@ -150,10 +198,7 @@ __device__ __forceinline__ void final_adjoint(const GridView &g, const int32_t *
         db[q] += o.eb[q];
         A.blk[q] += db[q];
       }
-      T *dst = gp + 3 * clamp_pos(id[b], g.n_points);
-      unsafeAtomicAdd(dst + 0, db[0] * ih);
-      unsafeAtomicAdd(dst + 1, db[1] * ih);
-      unsafeAtomicAdd(dst + 2, db[2] * ih);
+      tab.add((int32_t)clamp_pos(id[b], g.n_points), db[0] * ih, db[1] * ih, db[2] * ih);
     }
     A.fold();
   }
@@ -191,17 +236,15 @@ __device__ __forceinline__ void frame_u_adjoint(const double n[3], const double 
   else { nbar[0] += tb[1]; nbar[1] -= tb[0]; }
 }
 
+// Adjoint of the query in slot p; point gradients go through the table.
 template <bool kF32>
-__global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView qv, int32_t k,
-                                                         double support_radius_h,
-                                                         int32_t min_support,
-                                                         const int32_t *__restrict__ nbr,
-                                                         const void *__restrict__ grad_out,
-                                                         void *__restrict__ grad_q,
-                                                         Real<kF32> *__restrict__ gp) {
+__device__ __forceinline__ void backward_one(const GridView &g, const QueryView &qv, int32_t k,
+                                             double support_radius_h, int32_t min_support,
+                                             const int32_t *__restrict__ nbr,
+                                             const void *__restrict__ grad_out,
+                                             void *__restrict__ grad_q,
+                                             const ScatterTable<Real<kF32>> &tab, int64_t p) {
   using T = Real<kF32>;
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= qv.n) return;
   const int64_t qi = query_of_slot(g, qv, p);
   double r[3], gb[3];
   load_query(qv, qi, r);
@@ -215,27 +258,20 @@ __global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView q
   const double h = g.clouds[cloud].h;
   const int32_t *nb = nbr + (p >> 6) * 64 * k + (p & 63);
 
-  // statuses of the forward: support on canonical keys, any invalid entry
-  // makes the query an outlier
+  // statuses of the forward: support on canonical keys (counted during pass
+  // 1), any invalid entry makes the query an outlier
   const double rad = support_radius_h * h;
-  const double rad2 = rad * rad;
   int m = 0;
   bool valid = true;
-  for (int j = 0; j < k; ++j) {
-    const int32_t v = nb[j * 64];
-    valid = valid && v >= 0 && (int64_t)v < g.n_points;
-    const float4 P = g.pts[clamp_pos(v, g.n_points)];
-    m += canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]) <= rad2 ? 1 : 0;
-  }
+  const Rel<kF32> rel(r, 1.0 / h);
+  double S0, S1[3], S2[6];
+  pass1_moments<kF32, true>(g, nb, k, rel, S0, S1, S2, r, rad * rad, &m, &valid);
   if (!valid || m < min_support) {  // out = r
     store_vec(grad_q, qv.is_f64, qi, gb);
     return;
   }
 
   // ---- forward recompute ----------------------------------------------------
-  const Rel<kF32> rel(r, 1.0 / h);
-  double S0, S1[3], S2[6];
-  pass1_moments<kF32>(g, nb, k, rel, S0, S1, S2);
   const PlaneFit pf = plane_from_moments(S0, S1, S2, r, h);
   const FrameT<kF32> fr(pf);
   double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -328,11 +364,46 @@ __global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView q
 
   // ---- both passes' per-neighbour adjoint, scatter -------------------------------
   double D[3];
-  final_adjoint<kF32>(g, nb, k, rel, fr, aT, bbT, (T)Sb0, Sb1, Sb2, (T)(1.0 / h), gp, D);
+  final_adjoint<kF32>(g, nb, k, rel, fr, aT, bbT, (T)Sb0, Sb1, Sb2, (T)(1.0 / h), tab, D);
   const double ih = 1.0 / h;
   double rb[3];
   for (int q = 0; q < 3; ++q) rb[q] = gb[q] - D[q] * ih;
   store_vec(grad_q, qv.is_f64, qi, rb);
+}
+
+template <bool kF32>
+__global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView qv, int32_t k,
+                                                         double support_radius_h,
+                                                         int32_t min_support,
+                                                         const int32_t *__restrict__ nbr,
+                                                         const void *__restrict__ grad_out,
+                                                         void *__restrict__ grad_q,
+                                                         Real<kF32> *__restrict__ gp) {
+  using T = Real<kF32>;
+  using Tab = ScatterTable<T>;
+  __shared__ int32_t skey[Tab::kSlots];
+  __shared__ T sval[3 * Tab::kSlots];
+  for (int i = threadIdx.x; i < Tab::kSlots; i += kBlock) {
+    skey[i] = -1;
+    sval[i] = (T)0;
+    sval[Tab::kSlots + i] = (T)0;
+    sval[2 * Tab::kSlots + i] = (T)0;
+  }
+  __syncthreads();
+  const Tab tab{skey, sval, gp};
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p < qv.n)
+    backward_one<kF32>(g, qv, k, support_radius_h, min_support, nbr, grad_out, grad_q, tab, p);
+  __syncthreads();
+  for (int i = threadIdx.x; i < Tab::kSlots; i += kBlock) {
+    const int32_t pos = skey[i];
+    if (pos >= 0) {
+      T *dst = gp + 3 * (int64_t)pos;
+      unsafeAtomicAdd(dst + 0, sval[i]);
+      unsafeAtomicAdd(dst + 1, sval[Tab::kSlots + i]);
+      unsafeAtomicAdd(dst + 2, sval[2 * Tab::kSlots + i]);
+    }
+  }
 }
 
 // Caller lists (original indices, row-major per query) -> sorted positions in

@@ -192,19 +192,30 @@ __device__ __forceinline__ void load_batch(const GridView &g, const int32_t *nb,
 }
 
 // Pass 1: S0 = sum w, S1 = sum w d, S2 = sum w d d^T (packed 00 01 02 11 12 22).
-template <bool kF32>
+// With kSupport it also counts the list entries whose canonical FP64 key to r
+// is at most rad2 (into *m) and clears *valid if an entry is not a position.
+template <bool kF32, bool kSupport = false>
 __device__ __forceinline__ void pass1_moments(const GridView &g, const int32_t *nb, int k,
                                               const Rel<kF32> &rel, double &S0, double S1[3],
-                                              double S2[6]) {
+                                              double S2[6], const double *r = nullptr,
+                                              double rad2 = 0.0, int *m = nullptr,
+                                              bool *valid = nullptr) {
   using T = Real<kF32>;
   Acc<kF32, 10> A;
   A.zero();
   for (int j0 = 0; j0 < k; j0 += kBatch) {
     float4 PB[kBatch];
-    load_batch(g, nb, j0, k, PB);
+    int32_t id[kBatch];
+    load_batch(g, nb, j0, k, PB, id);
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       if (j0 + b >= k) break;
+      if constexpr (kSupport) {
+        *valid = *valid && id[b] >= 0 && (int64_t)id[b] < g.n_points;
+        const double key = canon_key((double)PB[b].x, (double)PB[b].y, (double)PB[b].z, r[0],
+                                     r[1], r[2]);
+        *m += key <= rad2 ? 1 : 0;
+      }
       T dx, dy, dz;
       rel.d(PB[b], dx, dy, dz);
       const T w = wexp(-(dx * dx + dy * dy + dz * dz));

@@ -188,3 +188,21 @@ def test_autograd_function():
     assert q.grad.dtype == torch.float64 and pts.grad.dtype == torch.float32
     assert torch.allclose(q.grad, gq, rtol=1e-12, atol=1e-15)
     assert torch.allclose(pts.grad.double(), gp, rtol=1e-6, atol=1e-9)
+
+
+def test_reuse_lists_of_preceding_search():
+    a = api()
+    P = synth.torus(50000, sigma=0.005, seed=2)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    gout = torch.from_numpy(np.random.default_rng(3).normal(size=P.shape).astype(np.float32)).cuda()
+    gq_fresh, gp_fresh = g.project_backward(Pt, gout, 32, "fp32")
+    g.project(Pt, 32, "fp32")
+    gq_reuse, gp_reuse = g.project_backward(Pt, gout, 32, "fp32", reuse_lists=True)
+    torch.cuda.synchronize()
+    # the same search ran in both: identical lists in identical order
+    assert torch.equal(gq_fresh, gq_reuse)
+    assert (gp_fresh - gp_reuse).norm() <= 1e-5 * gp_fresh.norm()
+    with pytest.raises(ValueError):
+        g.project_backward(Pt, gout, 32, "fp32", neighbors=torch.zeros((P.shape[0], 32), dtype=torch.int32, device="cuda"), reuse_lists=True)
