@@ -204,8 +204,14 @@ mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries,
  *   out_status     n_queries status bytes (MLS_PT_*).
  *   out_neighbors  nullable; as in mls_knn. Keep it to run the backward pass
  *                  without recomputing the lists.
+ * out_points and out_status may be NULL when params->stages is
+ * MLS_STAGE_SEARCH alone.
  * Iterated passes (the surface is approached by moving the queries) call this
- * again with the outputs as queries and the same grid. */
+ * again with the outputs as queries and the same grid.
+ * Graph capture: with query_offsets NULL the call only launches kernels on
+ * `stream` (no host copy, allocation, memset or wait), so it can be captured
+ * in a HIP graph and replayed; with query_offsets it first copies them to the
+ * device from host memory. */
 mls_status mls_project(const mls_grid *grid, const mls_params *params,
                        const void *queries, mls_dtype dtype, int64_t n_queries,
                        const int64_t *query_offsets, void *out_points,
@@ -263,6 +269,32 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
                                 void *grad_queries, void *grad_points,
                                 void *workspace, size_t workspace_bytes,
                                 void *stream);
+
+/* ---- tuning --------------------------------------------------------------
+ * Not in the paper: the grid hash replaces its k-d tree (Section 2.2), and
+ * the search cost of the hash depends on the finest cell edge. The tuner
+ * measures it.
+ *
+ * Bytes of device workspace mls_autotune_cell needs (host). */
+size_t mls_autotune_workspace_bytes(int64_t n_points, int32_t n_clouds,
+                                    int32_t k, int32_t stride);
+
+/* Picks the cell edge factor f (cell = f * h of each cloud) with the fastest
+ * neighbour search: for each candidate builds the grid and times (HIP events,
+ * second of two runs) the search stage of k neighbours for every stride-th
+ * point of each cloud as FP32 queries. Waits for the stream (host).
+ *   points, n_points, cloud_offsets, n_clouds, h   as in mls_build_grid.
+ *   candidates      host, n_candidates factors > 0.
+ *   best_factor     host out: the fastest candidate.
+ *   ms_per_candidate host out, nullable: n_candidates search times in ms.
+ * Errors as in mls_build_grid and mls_project. */
+mls_status mls_autotune_cell(const float *points, int64_t n_points,
+                             const int64_t *cloud_offsets, int32_t n_clouds,
+                             const double *h, int32_t k,
+                             const double *candidates, int32_t n_candidates,
+                             int32_t stride, void *workspace,
+                             size_t workspace_bytes, void *stream,
+                             double *best_factor, float *ms_per_candidate);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ fails loudly if the library has not been built.
 """
 import importlib
 
-__all__ = ["Grid", "build_grid", "project", "mls_project", "MLSProject"]
+__all__ = ["Grid", "build_grid", "project", "mls_project", "MLSProject", "autotune_cell_factor"]
 
 
 def __getattr__(name):

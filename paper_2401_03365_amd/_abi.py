@@ -50,6 +50,9 @@ SIGNATURES = {
     "mls_grid_sorted_points": (_ST, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "mls_project_workspace_bytes": (_SZ, [_P, _I32, _I64]),
     "mls_project_backward_workspace_bytes": (_SZ, [_P, _I32, _I64, _I32]),
+    "mls_autotune_workspace_bytes": (_SZ, [_I64, _I32, _I32, _I32]),
+    "mls_autotune_cell": (_ST, [_P, _I64, _P, _I32, _P, _I32, _P, _I32, _I32, _P, _SZ, _P, _P,
+                                _P]),
     "mls_knn": (_ST, [_P, _I32, _P, _ST, _I64, _P, _P, _P, _P, _SZ, _P]),
     "mls_project": (_ST, [_P, ctypes.POINTER(MlsParams), _P, _ST, _I64, _P, _P, _P, _P, _P,
                           _SZ, _P]),

@@ -51,7 +51,10 @@ class Grid:
     """Morton-sorted uniform-grid index of one cloud or a batch of clouds.
 
     ``h`` is the Gaussian width per cloud; ``cell_size`` (per cloud, or None)
-    the grid cell edge (default 3h)."""
+    the finest grid cell edge (default 1.25 h). Calls on the grid can be
+    captured in a HIP graph (queries aligned with the points, or one cloud
+    without query offsets); the grid and its workspaces must outlive the
+    graph."""
 
     def __init__(self, points: torch.Tensor, h, cloud_offsets=None, cell_size=None):
         lib = _abi.load()
@@ -83,6 +86,7 @@ class Grid:
         _abi.check(code, "mls_build_grid")
         self._handle = handle
         self._proj_ws = None
+        self._retired_ws = []
 
     # ---- facts ------------------------------------------------------------
     def info(self) -> dict:
@@ -123,6 +127,9 @@ class Grid:
         if nbytes == 0:
             raise ValueError("invalid k or query count")
         if self._proj_ws is None or self._proj_ws.numel() < nbytes:
+            if self._proj_ws is not None:
+                # a captured graph may still launch kernels on the old buffer
+                self._retired_ws.append(self._proj_ws)
             self._proj_ws = _workspace(nbytes, self.device)
         return self._proj_ws
 
@@ -213,6 +220,33 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+def autotune_cell_factor(points: torch.Tensor, h, k: int, cloud_offsets=None,
+                         candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0),
+                         stride: int = 16):
+    """Measures the neighbour search over every ``stride``-th point for each
+    candidate cell edge (factor x h) and returns (best factor, {factor: ms})."""
+    lib = _abi.load()
+    _check_points(points, "points")
+    n = points.shape[0]
+    offs, offs_p = _host_i64(cloud_offsets)
+    n_clouds = 1 if offs is None else len(offs) - 1
+    hh = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (n_clouds,)))
+    cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.float64))
+    ms = np.zeros(len(cand), dtype=np.float32)
+    nbytes = lib.mls_autotune_workspace_bytes(n, n_clouds, k, stride)
+    if nbytes == 0:
+        raise ValueError("invalid autotune arguments")
+    ws = _workspace(nbytes, points.device)
+    best = ctypes.c_double()
+    code = lib.mls_autotune_cell(_ptr(points), n, offs_p, n_clouds,
+                                 hh.ctypes.data_as(ctypes.c_void_p), int(k),
+                                 cand.ctypes.data_as(ctypes.c_void_p), len(cand), int(stride),
+                                 _ptr(ws), ws.numel(), _stream(), ctypes.byref(best),
+                                 ms.ctypes.data_as(ctypes.c_void_p))
+    _abi.check(code, "mls_autotune_cell")
+    return best.value, {float(c): float(t) for c, t in zip(cand, ms)}
 
 
 def build_grid(points, h, cloud_offsets=None, cell_size=None) -> Grid:

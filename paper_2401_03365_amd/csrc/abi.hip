@@ -92,6 +92,16 @@ size_t bwd_total(int32_t n_clouds, int32_t k, int64_t n, int64_t n_points, int32
   return bwd_gp_offset(n_clouds, k, n) + align256(3 * elem * (size_t)n_points);
 }
 
+}  // namespace
+
+namespace mls {
+size_t proj_workspace_bytes(int32_t n_clouds, int32_t k, int64_t n) {
+  return proj_layout(n_clouds, k, n).total;
+}
+}  // namespace mls
+
+namespace {
+
 bool offsets_ok(const int64_t *off, int32_t c, int64_t n) {
   if (off[0] != 0 || off[c] != n) return false;
   for (int32_t i = 0; i < c; ++i)
@@ -312,6 +322,7 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   gh.n_nonfinite = nonfinite_total;
   gh.min_cloud_finite = min_finite;
   gh.clouds_dev = clouds;
+  gh.offsets_dev = offsets_dev;
   gh.workspace = workspace;
   gh.workspace_bytes = workspace_bytes;
   *out_grid = G;
@@ -407,10 +418,16 @@ mls_status prepare_queries(const mls_grid *grid, int32_t k, const void *queries,
   qv->aligned = aligned ? 1 : 0;
   qv->qcloud = nullptr;
   if (C > 1 && n > 0) {
-    int64_t *off_dev = (int64_t *)(ws + L->offsets);
+    // queries aligned with the points take the grid's device offsets (no
+    // host copy, so the call can be captured in a graph); explicit query
+    // offsets are uploaded first
     int32_t *qcloud = (int32_t *)(ws + L->qcloud);
-    const int64_t *src = query_offsets ? query_offsets : g.offsets;
-    MLS_HIP(hipMemcpyAsync(off_dev, src, 8 * ((size_t)C + 1), hipMemcpyHostToDevice, s));
+    const int64_t *off_dev = g.offsets_dev;
+    if (query_offsets) {
+      int64_t *up = (int64_t *)(ws + L->offsets);
+      MLS_HIP(hipMemcpyAsync(up, query_offsets, 8 * ((size_t)C + 1), hipMemcpyHostToDevice, s));
+      off_dev = up;
+    }
     MLS_HIP(mls::launch_fill_cloud_ids(off_dev, C, n, qcloud, s));
     qv->qcloud = qcloud;
   }
@@ -450,7 +467,8 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params, const voi
       params->min_support < 0 || params->stages < 0 || params->stages > 3)
     return MLS_ERR_INVALID_ARGUMENT;
   const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
-  if (n_queries > 0 && (!out_points || !out_status)) return MLS_ERR_INVALID_ARGUMENT;
+  if (n_queries > 0 && (stages & MLS_STAGE_FIT) && (!out_points || !out_status))
+    return MLS_ERR_INVALID_ARGUMENT;
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;

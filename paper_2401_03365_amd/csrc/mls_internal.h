@@ -66,6 +66,7 @@ struct GridHost {
   int64_t n_nonfinite;
   int64_t min_cloud_finite;
   int64_t *offsets;          // host copy, n_clouds + 1
+  int64_t *offsets_dev;      // device copy, in the workspace
   int64_t *finite_counts;    // host, n_clouds
   CloudDev *clouds_host;     // host copy of the device table
   CloudDev *clouds_dev;      // in the workspace
@@ -176,6 +177,8 @@ hipError_t launch_mls_backward(const GridView &g, const QueryView &qv, int32_t k
                                int32_t precision, double support_radius_h, int32_t min_support,
                                const int32_t *nbr_tiles, const void *grad_out, void *grad_q,
                                void *gp_sorted, void *grad_points, hipStream_t s);
+// Bytes of the mls_project workspace (host).
+size_t proj_workspace_bytes(int32_t n_clouds, int32_t k, int64_t n);
 hipError_t launch_fill_cloud_ids(const int64_t *offsets_dev, int32_t n_clouds, int64_t n,
                                  int32_t *qcloud, hipStream_t s);
 }  // namespace mls
