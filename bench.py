@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--c4-n", type=int, default=2_000_000)
+    ap.add_argument("--no-batch", action="store_true")
     return ap.parse_args()
 
 
@@ -210,6 +211,126 @@ def heightfield_loss(torch, field):
     return grad
 
 
+def batch_loss_grad(torch, P, off, shapes, n_total):
+    """Elementwise gradient of L = mean_j res_j^2 over the batch with the
+    closed-form residual of each cloud's surface: sphere |y| - 1, torus
+    (R = 1, r = 0.3) sqrt((rho - R)^2 + z^2) - r, height field z - f(x, y)
+    with the cloud's own field. No reductions, so it can sit in a graph."""
+    from paper_2401_03365_amd import synth
+    kind = np.zeros(P.shape[0], dtype=np.int8)
+    hf_rows, alpha, phase = [], [], []
+    for c, sh in enumerate(shapes):
+        sl = slice(int(off[c]), int(off[c + 1]))
+        if sh == "torus":
+            kind[sl] = 1
+        elif sh == "heightfield":
+            kind[sl] = 2
+            f = synth.HeightField(5000 + c + 1000)
+            hf_rows.append(np.arange(off[c], off[c + 1]))
+            alpha.append(np.broadcast_to(f.alpha, (int(off[c + 1] - off[c]), 8)))
+            phase.append(np.broadcast_to(f.phase, (int(off[c + 1] - off[c]), 8)))
+            amp = f.amp
+    dev = "cuda"
+    kind_t = torch.from_numpy(kind).to(dev)
+    rows = torch.from_numpy(np.concatenate(hf_rows)).to(dev)
+    ca = torch.from_numpy(np.cos(np.concatenate(alpha)).astype(np.float32)).to(dev)
+    sa = torch.from_numpy(np.sin(np.concatenate(alpha)).astype(np.float32)).to(dev)
+    ph = torch.from_numpy(np.concatenate(phase).astype(np.float32)).to(dev)
+    fr = 2.0 * np.pi * torch.arange(1, 9, dtype=torch.float32, device=dev)
+    is_sph = (kind_t == 0)[:, None]
+    is_tor = (kind_t == 1)[:, None]
+    scale = 2.0 / n_total
+
+    def grad(y):
+        nrm = y.norm(dim=1, keepdim=True)
+        g_s = (nrm - 1.0) * y / nrm
+        rho = y[:, :2].norm(dim=1, keepdim=True)
+        dt = torch.sqrt((rho - 1.0) ** 2 + y[:, 2:] ** 2)
+        res_t = dt - 0.3
+        g_t = torch.cat([res_t * (rho - 1.0) / dt * y[:, :2] / rho, res_t * y[:, 2:] / dt], 1)
+        g = torch.where(is_sph, g_s, torch.where(is_tor, g_t, torch.zeros_like(y)))
+        yh = y[rows]
+        arg = fr * (yh[:, :1] * ca + yh[:, 1:2] * sa) + ph
+        res_h = yh[:, 2] - amp * torch.sin(arg).sum(1)
+        c = amp * torch.cos(arg) * fr
+        g_h = torch.stack([-res_h * (c * ca).sum(1), -res_h * (c * sa).sum(1), res_h], 1)
+        g = g.index_copy(0, rows, g_h)
+        return g * scale
+    return grad
+
+
+def batch_fwd_bwd(api, torch, steps, warmup):
+    """256 clouds (~30M points, sizes log-normal, sphere / torus / height
+    field, per-cloud h), k = 32, FP32: the cell edge is tuned, the grid built
+    once, then [search, fit, loss gradient, adjoint] is captured in one HIP
+    graph and replayed. value = N / (time of one replay)."""
+    from paper_2401_03365_amd import synth
+    t = time.perf_counter()
+    P, off, sig, shapes = synth.batch()
+    h = np.array([synth.mean_nn_h(P[off[c]:off[c + 1]]) for c in range(len(off) - 1)])
+    log("batch: %d clouds, %d pts generated (%.1f s)" % (len(h), P.shape[0], time.perf_counter() - t))
+    pts = torch.from_numpy(P).cuda()
+    k = 32
+    t = time.perf_counter()
+    best, ms = api.autotune_cell_factor(pts, h, k, cloud_offsets=off)
+    tune_s = time.perf_counter() - t
+    log("batch: tuned cell factor %.2f %s (%.1f s)" % (best, ms, tune_s))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    grid = api.Grid(pts, h, cloud_offsets=off, cell_size=best * h)
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    loss_grad = batch_loss_grad(torch, P, off, shapes, P.shape[0])
+    out = torch.empty_like(pts)
+    status = torch.empty((pts.shape[0],), dtype=torch.uint8, device="cuda")
+
+    def body():
+        grid.project(pts, k, "fp32", stages=1, out=out, status=status)
+        grid.project(pts, k, "fp32", stages=2, out=out, status=status)
+        gy = loss_grad(out)
+        return grid.project_backward(pts, gy, k, "fp32", reuse_lists=True)
+
+    for _ in range(warmup):
+        body()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        body()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        body()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gq, gp = body()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    ok = bool(torch.isfinite(gq).all().item() and torch.isfinite(gp).all().item())
+    gq_g, gp_g = gq.clone(), gp.clone()
+    gq_e, gp_e = body()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(gq_g, gq_e)) and \
+        float((gp_g - gp_e).norm() / gp_e.norm()) <= 1e-5
+    log("batch: graph %.2f ms/step, eager %.2f ms/step, build %.2f ms, finite grads %s" %
+        (graph_ms, eager_ms, build_ms, ok))
+    return {"value": P.shape[0] / (graph_ms / 1000.0), "unit": "pts/s",
+            "n_points": int(P.shape[0]), "n_clouds": int(len(h)), "k": k,
+            "ms_per_step_graph": graph_ms, "ms_per_step_eager": eager_ms, "build_ms": build_ms,
+            "cell_factor": best, "autotune_ms": ms, "grads_finite": ok,
+            "graph_matches_eager": same,
+            "step": "search + fit + loss gradient + adjoint, one graph replay"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -287,6 +408,8 @@ def main():
         h4 = synth.mean_nn_h(P4)
         fb["sh_sphere_2M_k32"] = fwd_bwd(api, torch, P4, h4, 32, sh_sphere_loss(torch, shf, P4),
                                          args.steps, args.warmup, "fwd+bwd sh sphere")
+        if not args.no_batch:
+            fb["batch_256_clouds_30M_k32"] = batch_fwd_bwd(api, torch, args.steps, args.warmup)
         res["fwd_bwd"] = fb
 
     if not args.no_cpu_baseline:
