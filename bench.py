@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--c4-n", type=int, default=2_000_000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a device-to-device copy of this many MB (3 times) and "
+                         "print its bandwidth: the reference for the HBM traffic counters")
     return ap.parse_args()
 
 
@@ -339,6 +342,21 @@ def main():
         sys.exit(2)
     import torch
     from paper_2401_03365_amd import api, synth
+
+    if args.copy_calibration_mb:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            e0.record()
+            dst.copy_(src)
+            e1.record()
+            torch.cuda.synchronize()
+            log("copy %d MiB: %.3f ms, %.1f GB/s (read + write)" %
+                (args.copy_calibration_mb, e0.elapsed_time(e1), 2 * nbytes / e0.elapsed_time(e1) / 1e6))
+        print(json.dumps({"copy_bytes": nbytes, "ms": e0.elapsed_time(e1)}), flush=True)
+        return
 
     t = time.perf_counter()
     P, hfield = synth.heightfield(args.n, sigma=1e-3, seed=3, return_field=True)

@@ -502,7 +502,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
   WaveLds &L = lds[wv];
   const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
   const int nopt = 2 * g.n_levels;
-  for (int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wv; task < nchunks;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t task = blk * kWavesPerBlock + wv; task < nchunks;
        task += (int64_t)gridDim.x * kWavesPerBlock) {
     // cache of the staged block: its cell, option and cloud, the candidate
     // count and the candidate coordinates (positions and indices live in the

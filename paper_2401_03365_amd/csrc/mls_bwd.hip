@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView q
   }
   __syncthreads();
   const Tab tab{skey, sval, gp};
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (p < qv.n)
     backward_one<kF32>(g, qv, k, support_radius_h, min_support, nbr, grad_out, grad_q, tab, p);
   __syncthreads();

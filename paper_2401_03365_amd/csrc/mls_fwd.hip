@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
                                                         const uint8_t *__restrict__ support,
                                                         void *__restrict__ out,
                                                         uint8_t *__restrict__ status) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (p >= qv.n) return;
   const int64_t qi = query_of_slot(g, qv, p);
   double r[3];

@@ -41,6 +41,16 @@ __device__ __forceinline__ double canon_key(double px, double py, double pz, dou
   return (sx + sy) + sz;
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (XCD = id mod 8). Renumbering
+// gives each XCD one contiguous range of block numbers, so work that is
+// adjacent in Morton order (and shares cells, table lines and neighbours)
+// runs on the same XCD and meets in its L2. A bijection of [0, nb) for any nb.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t x = b & 7, i = b >> 3;
+  const uint32_t per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // Device-resident view of a built grid, passed to kernels by value.
 struct GridView {
   const float4 *pts;         // sorted points, w = original index bits
