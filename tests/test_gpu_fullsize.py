@@ -1,0 +1,147 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (queries aligned with the cloud's points, one call over the
+whole cloud), on sampled queries that the oracle computes one by one with
+brute-force kNN over the whole cloud:
+
+  torus 1,010,000 (1 % outliers), k = 32, FP32-moment and FP64 paths;
+  height field 10,000,000, k = 48, 3 iterated FP32-moment passes (each pass
+      checked against the oracle fed the GPU's own pass input);
+  bumped sphere 2,000,000, k = 32, FP32 forward and the adjoint (1,000
+      queries against central finite differences);
+  batch of 256 clouds, ~30M points, k = 32, FP32.
+
+Bars as in the small-size tests: neighbour lists and statuses bit for bit,
+FP64 max error <= 1e-10 h, FP32-moment RMS <= 1e-5 h (points whose normal is
+flagged ambiguous excluded from max errors), adjoint <= 1e-4 relative."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_03365_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_MAX_H = 1e-10
+FP32_RMS_H = 1e-5
+
+
+def api():
+    from paper_2401_03365_amd import api as a
+    return a
+
+
+def check_sample(orc, P64, Qs, k, h, out, st, nbr, precision):
+    """Qs: the sampled queries of the pass input (FP64); out/st/nbr: the GPU
+    results for them."""
+    ref_nbr, _ = orc.knn(P64, Qs, k)
+    np.testing.assert_array_equal(nbr, ref_nbr)
+    ref, ref_st = orc.project(P64, Qs, k, h, nbr=ref_nbr)
+    np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    diff = np.abs(out.astype(np.float64) - ref)
+    if out.dtype == np.float32:
+        diff = np.maximum(diff - np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
+    err = np.linalg.norm(diff, axis=1)[ok] / h
+    if precision == "fp64":
+        assert err.max() <= FP64_MAX_H, err.max()
+    else:
+        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
+
+
+def run_pass(g, q, k, precision, idx_t):
+    out, st, nbr = g.project(q, k, precision, return_neighbors=True)
+    torch.cuda.synchronize()
+    return out, st, nbr[idx_t].cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_torus_1m_with_outliers(orc, precision):
+    P, mask = synth.torus(1_000_000, sigma=0.005, n_outliers=10_000, seed=2, return_mask=True)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    rng = np.random.default_rng(21)
+    idx = np.concatenate([rng.choice(1_000_000, 400, replace=False),
+                          1_000_000 + rng.choice(10_000, 100, replace=False)])
+    idx_t = torch.from_numpy(idx).cuda()
+    q = Pt.double()
+    out, st, nbr = run_pass(g, q, 32, precision, idx_t)
+    P64 = P.astype(np.float64)
+    check_sample(orc, P64, P64[idx], 32, h, out[idx_t].cpu().numpy(),
+                 st[idx_t].cpu().numpy(), nbr, precision)
+    assert ((st[idx_t[400:]] & 0x0F) == 1).sum().item() > 50  # most outliers flagged
+
+
+def test_heightfield_10m_three_passes(orc):
+    P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h, cell_size=1.25 * h)
+    rng = np.random.default_rng(22)
+    idx = np.sort(rng.choice(P.shape[0], 192, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    P64 = P.astype(np.float64)
+    cur = Pt.double()
+    for it in range(3):
+        out, st, nbr = run_pass(g, cur, 48, "fp32", idx_t)
+        check_sample(orc, P64, cur[idx_t].cpu().numpy(), 48, h, out[idx_t].cpu().numpy(),
+                     st[idx_t].cpu().numpy(), nbr, "fp32")
+        cur = out
+
+
+def test_bumped_sphere_2m_forward_and_adjoint(orc):
+    P = synth.sh_sphere(2_000_000, sigma=0.005, seed=4)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h, cell_size=1.25 * h)
+    rng = np.random.default_rng(23)
+    idx = np.sort(rng.choice(P.shape[0], 1000, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    out, st, nbr = run_pass(g, Pt, 32, "fp32", idx_t)
+    P64 = P.astype(np.float64)
+    check_sample(orc, P64, P64[idx[:300]], 32, h, out[idx_t[:300]].cpu().numpy(),
+                 st[idx_t[:300]].cpu().numpy(), nbr[:300], "fp32")
+    # adjoint: the full aligned call (as timed) and the 1,000 sampled queries
+    gout = torch.from_numpy(rng.normal(size=P.shape).astype(np.float32)).cuda()
+    gq_full, _ = g.project_backward(Pt, gout, 32, "fp32")
+    Qs = P64[idx]
+    ref_nbr, _ = orc.knn(P64, Qs, 32)
+    _, ref_st = orc.project(P64, Qs, 32, h, nbr=ref_nbr)
+    keep = (ref_st & 0x10) == 0
+    Qs, ref_nbr = Qs[keep], ref_nbr[keep]
+    go = gout[idx_t].cpu().numpy().astype(np.float64)[keep]
+    fq, fp = orc.grad_fd(P64, Qs, 32, h, ref_nbr, go)
+    Qt = torch.from_numpy(Qs).cuda()
+    gq, gp = g.project_backward(Qt, torch.from_numpy(go).cuda(), 32, "fp32",
+                                neighbors=torch.from_numpy(ref_nbr).cuda())
+    torch.cuda.synchronize()
+    gq, gp = gq.cpu().numpy(), gp.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gq - fq) <= 1e-4 * np.linalg.norm(fq)
+    assert np.linalg.norm(gp - fp) <= 1e-4 * np.linalg.norm(fp)
+    # the full call's query gradients agree with the sampled call's
+    gfull = gq_full[idx_t].cpu().numpy().astype(np.float64)[keep]
+    assert np.linalg.norm(gfull - gq) <= 1e-5 * np.linalg.norm(gq)
+
+
+def test_batch_256_clouds(orc):
+    P, off, sig, shapes = synth.batch()
+    a = api()
+    sel = [0, 1, 2, 100, 177, 255]  # sphere, torus, height field, ...
+    h = np.array([synth.mean_nn_h(P[off[c]:off[c + 1]]) for c in range(len(off) - 1)])
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h, cloud_offsets=off, cell_size=2.0 * h)
+    rng = np.random.default_rng(24)
+    idx = np.concatenate([off[c] + rng.choice(off[c + 1] - off[c], 48, replace=False)
+                          for c in sel])
+    idx_t = torch.from_numpy(idx).cuda()
+    out, st, nbr = run_pass(g, Pt, 32, "fp32", idx_t)
+    out_s, st_s = out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy()
+    for j, c in enumerate(sel):
+        rows = slice(48 * j, 48 * (j + 1))
+        Pc = P[off[c]:off[c + 1]].astype(np.float64)
+        local = idx[rows] - off[c]
+        check_sample(orc, Pc, Pc[local], 32, h[c], out_s[rows], st_s[rows],
+                     nbr[rows] - off[c], "fp32")
