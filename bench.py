@@ -36,6 +36,13 @@ FP64_PEAK_TFLOPS = 78.6
 # projection): FP32 operations per neighbour (pass 1: 34, pass 2: 74; an
 # exponential counted as one operation each pass) plus the FP64 per-point
 # algebra (eigen-solve, frame, 6x6 Cholesky and solve: ~1,000 operations).
+# List refresh for later passes (MLS_STAGE_REFRESH): off. Measured on the 10M
+# height field, k = 48: the first pass moves the queries by 0.23 h (median),
+# so a refresh of pass 2 certifies only 59 % of the lists with 16 extra
+# neighbours, and a refresh of pass 3 from a 64-neighbour pass-2 search saves
+# only ~2 ms of 122 ms of search per step.
+SEARCH_EXTRA = 0
+REFRESH_FROM = 0
 FIT_FLOPS_PER_NEIGHBOUR = 108 + 2
 FIT_FP64_FLOPS_PER_QUERY = 1000
 # Algorithmic work of the exact search per query: 200 candidate FP64 keys of
@@ -148,10 +155,16 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
         status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
         for p in range(passes):
             nxt = torch.empty_like(cur)
-            with ctx("search"):
-                grid.project(cur, k, precision, stages=1, out=nxt, status=status)
+            # with REFRESH_FROM > 0, the searches keep SEARCH_EXTRA more
+            # neighbours and the passes from REFRESH_FROM on refresh the lists
+            # of the pass before (exact; a fresh search where not certified)
+            refresh = 0 < REFRESH_FROM <= p
+            with ctx("refresh" if refresh else "search"):
+                grid.project(cur, k, precision, stages=1, out=nxt, status=status,
+                             search_extra=SEARCH_EXTRA, refresh=refresh)
             with ctx("fit"):
-                grid.project(cur, k, precision, stages=2, out=nxt, status=status)
+                grid.project(cur, k, precision, stages=2, out=nxt, status=status,
+                             search_extra=SEARCH_EXTRA)
             if p == 0:
                 first = nxt
             cur = nxt
@@ -403,9 +416,9 @@ def main():
     timer = Timer(torch)
     ms32, first32, out32 = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", cell,
                                      args.steps, args.warmup, timer)
-    br32 = {n: timer.ms(n) for n in ("build", "search", "fit")}
-    log("fp32: %.2f ms/step  build %.2f  search %.2f  fit %.2f (ms per call)" %
-        (ms32, br32["build"], br32["search"], br32["fit"]))
+    br32 = {n: timer.ms(n) for n in ("build", "search", "refresh", "fit")}
+    log("fp32: %.2f ms/step  build %.2f  search %.2f  refresh %.2f  fit %.2f (ms per call)" %
+        (ms32, br32["build"], br32["search"], br32["refresh"], br32["fit"]))
     value = args.n * args.passes / (ms32 / 1000.0)
 
     fp64 = None
@@ -414,9 +427,9 @@ def main():
         timer64 = Timer(torch)
         ms64, first64, _ = run_steps(api, torch, pts, h, args.k, args.passes, "fp64", cell,
                                      max(1, args.steps // 2), 1, timer64)
-        br64 = {n: timer64.ms(n) for n in ("build", "search", "fit")}
-        log("fp64: %.2f ms/step  build %.2f  search %.2f  fit %.2f" %
-            (ms64, br64["build"], br64["search"], br64["fit"]))
+        br64 = {n: timer64.ms(n) for n in ("build", "search", "refresh", "fit")}
+        log("fp64: %.2f ms/step  build %.2f  search %.2f  refresh %.2f  fit %.2f" %
+            (ms64, br64["build"], br64["search"], br64["refresh"], br64["fit"]))
         fp64 = {"value": args.n * args.passes / (ms64 / 1000.0), "unit": "pts/s",
                 "ms_per_step": ms64, "breakdown_ms": br64}
 

@@ -91,16 +91,31 @@ typedef struct {
   double support_radius_h;  /* outlier radius in units of h (default 3.0) */
   int32_t min_support;      /* outlier threshold (default 3) */
   int32_t stages;           /* mls_stage bits; 0 = MLS_STAGE_ALL */
+  int32_t search_extra;     /* extra neighbours the search keeps per query
+                               beyond k (k + search_extra <= MLS_MAX_K), for
+                               MLS_STAGE_REFRESH in later passes; 0 = none */
 } mls_params;
 
 /* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and
  * support counts in the workspace; a later call with MLS_STAGE_FIT on the
  * same grid, queries, k, query_offsets and workspace (stream-ordered after
- * it) fits and projects from them, so one search can serve several fits. */
+ * it) fits and projects from them, so one search can serve several fits.
+ * MLS_STAGE_REFRESH (with MLS_STAGE_SEARCH) serves iterated passes (the
+ * method moves the queries iteratively, Section 1.4), where the queries move
+ * a little between passes and the cloud stays: instead of
+ * searching every query afresh, the lists of k + search_extra points the
+ * previous search left in this workspace (same grid, k, search_extra, query
+ * slots) are re-ranked by the canonical key for the new query positions. A
+ * list holds every point within the distance R of the query it was searched
+ * for (R = its last entry's distance), so when the new k-th distance is below
+ * R minus the query's displacement, the k nearest are in the list (triangle
+ * inequality) and the re-ranked list is the exact result; every other query
+ * is searched afresh. The result is the same as a fresh search. */
 typedef enum {
   MLS_STAGE_ALL = 0,
   MLS_STAGE_SEARCH = 1,
-  MLS_STAGE_FIT = 2
+  MLS_STAGE_FIT = 2,
+  MLS_STAGE_REFRESH = 4
 } mls_stage;
 
 /* Library version string (host). */
@@ -181,7 +196,8 @@ mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
  * query belongs to it.
  *
  * Bytes of device workspace mls_project / mls_knn need for n_queries
- * queries with k neighbours (host). */
+ * queries with k neighbours kept per query (for mls_project and
+ * mls_project_backward: params->k + params->search_extra) (host). */
 size_t mls_project_workspace_bytes(const mls_grid *grid, int32_t k,
                                    int64_t n_queries);
 

@@ -146,29 +146,36 @@ class Grid:
         _abi.check(code, "mls_knn")
         return (nbr, keys) if return_keys else nbr
 
-    def _params(self, k, precision, support_radius_h, min_support, stages=0):
+    def _params(self, k, precision, support_radius_h, min_support, stages=0, search_extra=0):
         if precision not in PRECISIONS:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
                               support_radius_h=float(support_radius_h),
-                              min_support=int(min_support), stages=int(stages))
+                              min_support=int(min_support), stages=int(stages),
+                              search_extra=int(search_extra))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
                 support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
-                status: Optional[torch.Tensor] = None):
+                status: Optional[torch.Tensor] = None, search_extra: int = 0,
+                refresh: bool = False):
         """One MLS projection pass. Returns (out, status[, neighbours]).
         ``stages``: 0 = search and fit, 1 = search only (lists stay in the
-        grid's workspace), 2 = fit only from the preceding search."""
+        grid's workspace), 2 = fit only from the preceding search.
+        ``search_extra``: neighbours kept beyond k for later refreshes;
+        ``refresh``: start the search from the lists of the previous search
+        of the same queries' slots (exact; see MLS_STAGE_REFRESH)."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
-        params = self._params(k, precision, support_radius_h, min_support, stages)
+        if refresh:
+            stages = (stages or (_abi.MLS_STAGE_SEARCH | _abi.MLS_STAGE_FIT)) | _abi.MLS_STAGE_REFRESH
+        params = self._params(k, precision, support_radius_h, min_support, stages, search_extra)
         if out is None:
             out = torch.empty_like(queries)
         if status is None:
             status = torch.empty((n,), dtype=torch.uint8, device=self.device)
         nbr = torch.empty((n, k), dtype=torch.int32, device=self.device) if return_neighbors else None
-        ws = self._proj_workspace(k, n)
+        ws = self._proj_workspace(k + search_extra, n)
         qo, qo_p = _host_i64(query_offsets)
         code = _abi.load().mls_project(self._handle, ctypes.byref(params), _ptr(queries),
                                        _dtype_code(queries), n, qo_p, _ptr(out), _ptr(status),
@@ -179,7 +186,7 @@ class Grid:
     def project_backward(self, queries: torch.Tensor, grad_out: torch.Tensor, k: int,
                          precision: str = "fp32", neighbors: Optional[torch.Tensor] = None,
                          query_offsets=None, support_radius_h: float = 3.0, min_support: int = 3,
-                         reuse_lists: bool = False):
+                         reuse_lists: bool = False, search_extra: int = 0):
         """Adjoint of one pass with lists and statuses fixed: returns
         (grad_queries, grad_points), both in the queries' dtype.
         ``neighbors``: the (n, k) int32 original-index lists of the forward
@@ -189,7 +196,7 @@ class Grid:
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
         stages = _abi.MLS_STAGE_FIT if reuse_lists else 0
-        params = self._params(k, precision, support_radius_h, min_support, stages)
+        params = self._params(k, precision, support_radius_h, min_support, stages, search_extra)
         lib = _abi.load()
         if grad_out.shape != queries.shape:
             raise ValueError("grad_out must have the shape of queries")
@@ -202,7 +209,7 @@ class Grid:
             neighbors = neighbors.contiguous()
         gq = torch.empty_like(queries)
         gp = torch.empty((self.n_points, 3), dtype=queries.dtype, device=self.device)
-        ws = self._proj_workspace(k, n)
+        ws = self._proj_workspace(k + search_extra, n)
         qo, qo_p = _host_i64(query_offsets)
         code = lib.mls_project_backward(
             self._handle, ctypes.byref(params), _ptr(queries), _dtype_code(queries), n, qo_p,
@@ -260,7 +267,7 @@ def project(points: torch.Tensor, h, k: int, precision: str = "fp32", passes: in
     grid = Grid(points, h, cloud_offsets=cloud_offsets, cell_size=cell_size)
     cur = points
     st = None
-    for _ in range(passes):
+    for it in range(passes):
         out, st_new = grid.project(cur, k, precision)
         if st is not None:
             frozen = (st & 0x0F) == _abi.PT_OUTLIER

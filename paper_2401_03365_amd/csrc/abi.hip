@@ -64,18 +64,21 @@ GridLayout grid_layout(int64_t n, int32_t c) {
 
 // Byte layout of the projection workspace.
 struct ProjLayout {
-  size_t nbr, support, qcloud, offsets, total;
+  size_t nbr, support, qcloud, offsets, anchor, flag, total;
 };
 
-ProjLayout proj_layout(int32_t n_clouds, int32_t k, int64_t n) {
+// k_list: entries kept per query (k plus the search's extra neighbours).
+ProjLayout proj_layout(int32_t n_clouds, int32_t k_list, int64_t n) {
   ProjLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
   // neighbour lists in tiles of 64 queries (the last tile padded)
-  L.nbr = take(4 * (size_t)((n + 63) / 64) * 64 * (size_t)k);
+  L.nbr = take(4 * (size_t)((n + 63) / 64) * 64 * (size_t)k_list);
   L.support = take((size_t)n);
   L.qcloud = take(n_clouds > 1 ? 4 * (size_t)n : 0);
   L.offsets = take(8 * ((size_t)n_clouds + 1));
+  L.anchor = take(32 * (size_t)n);  // per slot: the searched query and its bound
+  L.flag = take((size_t)n);         // per slot: left to a fresh search
   L.total = o;
   return L;
 }
@@ -389,11 +392,13 @@ size_t mls_project_backward_workspace_bytes(const mls_grid *grid, int32_t k, int
 namespace {
 
 // Shared validation and set-up of mls_knn / mls_project / mls_project_backward.
-mls_status prepare_queries(const mls_grid *grid, int32_t k, const void *queries, mls_dtype dtype,
-                           int64_t n, const int64_t *query_offsets, void *workspace,
-                           size_t workspace_bytes, hipStream_t s, mls::QueryView *qv,
-                           ProjLayout *L) {
-  if (!grid || k < 1 || k > MLS_MAX_K || n < 0 || n > 0x7fffffffll) return MLS_ERR_INVALID_ARGUMENT;
+mls_status prepare_queries(const mls_grid *grid, int32_t k, int32_t k_list, const void *queries,
+                           mls_dtype dtype, int64_t n, const int64_t *query_offsets,
+                           void *workspace, size_t workspace_bytes, hipStream_t s,
+                           mls::QueryView *qv, ProjLayout *L) {
+  if (!grid || k < 1 || k > MLS_MAX_K || k_list < k || k_list > MLS_MAX_K || n < 0 ||
+      n > 0x7fffffffll)
+    return MLS_ERR_INVALID_ARGUMENT;
   if (dtype != MLS_F32 && dtype != MLS_F64) return MLS_ERR_INVALID_ARGUMENT;
   if (n > 0 && (!queries || !workspace)) return MLS_ERR_INVALID_ARGUMENT;
   const mls::GridHost &g = grid->g;
@@ -405,7 +410,7 @@ mls_status prepare_queries(const mls_grid *grid, int32_t k, const void *queries,
   } else if (C > 1 && !aligned) {
     return MLS_ERR_INVALID_ARGUMENT;
   }
-  *L = proj_layout(C, k, n);
+  *L = proj_layout(C, k_list, n);
   if (n > 0 && ((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
   if (n > 0 && workspace_bytes < L->total) return MLS_ERR_WORKSPACE_TOO_SMALL;
   mls_status st = check_async();
@@ -417,6 +422,7 @@ mls_status prepare_queries(const mls_grid *grid, int32_t k, const void *queries,
   qv->order = nullptr;
   qv->aligned = aligned ? 1 : 0;
   qv->qcloud = nullptr;
+  qv->kstride = k_list;
   if (C > 1 && n > 0) {
     // queries aligned with the points take the grid's device offsets (no
     // host copy, so the call can be captured in a graph); explicit query
@@ -446,12 +452,13 @@ mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries, mls_dty
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
-  mls_status st = prepare_queries(grid, k, queries, dtype, n_queries, query_offsets, workspace,
-                                  workspace_bytes, s, &qv, &L);
+  mls_status st = prepare_queries(grid, k, k, queries, dtype, n_queries, query_offsets,
+                                  workspace, workspace_bytes, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
   char *ws = (char *)workspace;
-  MLS_HIP(mls::launch_knn(grid->g.view, qv, k, 3.0, (int32_t *)(ws + L.nbr),
-                          (uint8_t *)(ws + L.support), out_neighbors, out_keys, s));
+  MLS_HIP(mls::launch_knn(grid->g.view, qv, k, k, 3.0, false, (int32_t *)(ws + L.nbr),
+                          (uint8_t *)(ws + L.support), (double *)(ws + L.anchor),
+                          (uint8_t *)(ws + L.flag), out_neighbors, out_keys, s));
   return MLS_OK;
 }
 
@@ -464,23 +471,29 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params, const voi
   if (params->precision != MLS_PREC_FP64 && params->precision != MLS_PREC_FP32_MOMENTS)
     return MLS_ERR_INVALID_ARGUMENT;
   if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
-      params->min_support < 0 || params->stages < 0 || params->stages > 3)
+      params->min_support < 0 || params->stages < 0 || params->stages > 7 ||
+      params->search_extra < 0 || params->search_extra > MLS_MAX_K)
     return MLS_ERR_INVALID_ARGUMENT;
   const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
+  if ((stages & MLS_STAGE_REFRESH) && !(stages & MLS_STAGE_SEARCH))
+    return MLS_ERR_INVALID_ARGUMENT;
   if (n_queries > 0 && (stages & MLS_STAGE_FIT) && (!out_points || !out_status))
     return MLS_ERR_INVALID_ARGUMENT;
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
-  mls_status st = prepare_queries(grid, params->k, queries, dtype, n_queries, query_offsets,
-                                  workspace, workspace_bytes, s, &qv, &L);
+  const int32_t k_list = params->k + params->search_extra;
+  mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
+                                  query_offsets, workspace, workspace_bytes, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
   uint8_t *support = (uint8_t *)(ws + L.support);
   if (stages & MLS_STAGE_SEARCH)
-    MLS_HIP(mls::launch_knn(grid->g.view, qv, params->k, params->support_radius_h, nbr, support,
-                            out_neighbors, nullptr, s));
+    MLS_HIP(mls::launch_knn(grid->g.view, qv, k_list, params->k, params->support_radius_h,
+                            (stages & MLS_STAGE_REFRESH) != 0, nbr, support,
+                            (double *)(ws + L.anchor), (uint8_t *)(ws + L.flag), out_neighbors,
+                            nullptr, s));
   if (stages & MLS_STAGE_FIT)
     MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
                                     params->min_support, nbr, support, out_points, out_status,
@@ -498,8 +511,9 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   if (params->precision != MLS_PREC_FP64 && params->precision != MLS_PREC_FP32_MOMENTS)
     return MLS_ERR_INVALID_ARGUMENT;
   if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
-      params->min_support < 0)
+      params->min_support < 0 || params->search_extra < 0 || params->search_extra > MLS_MAX_K)
     return MLS_ERR_INVALID_ARGUMENT;
+  const int32_t k_list = params->k + params->search_extra;
   // stages: ALL = lists from `neighbors` or a fresh search; FIT = the lists a
   // preceding search left in this workspace
   const bool reuse = params->stages == MLS_STAGE_FIT;
@@ -509,15 +523,15 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   if (n_queries > 0 && (!grad_out || !grad_queries)) return MLS_ERR_INVALID_ARGUMENT;
   // the point gradients are accumulated in the workspace even without queries
   if (!grad_points || !workspace) return MLS_ERR_INVALID_ARGUMENT;
-  if (params->k >= 1 && params->k <= MLS_MAX_K && n_queries >= 0 &&
-      workspace_bytes < bwd_total(grid->g.n_clouds, params->k, n_queries, grid->g.n_points,
+  if (params->k >= 1 && k_list <= MLS_MAX_K && n_queries >= 0 &&
+      workspace_bytes < bwd_total(grid->g.n_clouds, k_list, n_queries, grid->g.n_points,
                                   params->precision))
     return MLS_ERR_WORKSPACE_TOO_SMALL;
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
-  mls_status st = prepare_queries(grid, params->k, queries, dtype, n_queries, query_offsets,
-                                  workspace, workspace_bytes, s, &qv, &L);
+  mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
+                                  query_offsets, workspace, workspace_bytes, s, &qv, &L);
   if (st != MLS_OK) return st;
   if (((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
   char *ws = (char *)workspace;
@@ -526,10 +540,11 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
     if (neighbors)
       MLS_HIP(mls::launch_lists_from_caller(grid->g.view, qv, params->k, neighbors, nbr, s));
     else
-      MLS_HIP(mls::launch_knn(grid->g.view, qv, params->k, params->support_radius_h, nbr,
-                              (uint8_t *)(ws + L.support), nullptr, nullptr, s));
+      MLS_HIP(mls::launch_knn(grid->g.view, qv, k_list, params->k, params->support_radius_h,
+                              false, nbr, (uint8_t *)(ws + L.support), (double *)(ws + L.anchor),
+                              (uint8_t *)(ws + L.flag), nullptr, nullptr, s));
   }
-  void *gp = ws + bwd_gp_offset(grid->g.n_clouds, params->k, n_queries);
+  void *gp = ws + bwd_gp_offset(grid->g.n_clouds, k_list, n_queries);
   MLS_HIP(mls::launch_mls_backward(grid->g.view, qv, params->k, params->precision,
                                    params->support_radius_h, params->min_support, nbr, grad_out,
                                    grad_queries, gp, grad_points, s));

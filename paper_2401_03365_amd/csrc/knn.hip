@@ -257,6 +257,26 @@ __device__ int compact(Slots &s, const bool keep[kSlots], WaveLds &L, int lane) 
   return ntop;
 }
 
+// Sorts the (key, index, position) triples held one per lane ascending by
+// (key, index) across the wave (bitonic network over 64 lanes).
+__device__ __forceinline__ void sort_lanes(uint64_t &mk, int32_t &mi, int32_t &mp, int lane) {
+  for (int size = 2; size <= 64; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t ok = shfl_xor_u64(mk, stride);
+      const int32_t oi = __shfl_xor(mi, stride);
+      const int32_t op = __shfl_xor(mp, stride);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      const bool olt = pair_lt(ok, oi, mk, mi);
+      const bool ogt = pair_lt(mk, mi, ok, oi);
+      const bool take = (lower == up) ? olt : ogt;
+      mk = take ? ok : mk;
+      mi = take ? oi : mi;
+      mp = take ? op : mp;
+    }
+  }
+}
+
 // Largest (key, index) pair of the running top-k.
 __device__ void top_max(const Slots &s, int ntop, int lane, uint64_t &kmax, int32_t &imax) {
   uint64_t mk = lane < ntop ? s.key[0] : 0;
@@ -490,10 +510,20 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
 __constant__ int8_t kOptLevel[2 * kMaxLevels] = {0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 5, 5, 6, 6, 7, 7};
 __constant__ int8_t kOptHalf[2 * kMaxLevels] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
 
+// Searches the k (= kfit + extra) nearest of every query slot (only the
+// slots flagged in slot_flag when it is given). The tile list of a slot holds
+// its k entries, sorted by (key, index) whenever k > kfit or sorted output is
+// wanted, so that the first kfit are the kfit nearest; the support count and
+// the caller's lists cover the first kfit. The slot's anchor (the query) and
+// bound (the k-th key: every point outside the list is at least that far, in
+// squared distance, from the anchor; +inf when the list holds the whole
+// cloud, -1 for a non-finite query) serve later refreshes.
 __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
-                                                            double support_r_h,
+                                                            int32_t kfit, double support_r_h,
                                                             int32_t *__restrict__ nbr,
                                                             uint8_t *__restrict__ support,
+                                                            double *__restrict__ anchor,
+                                                            const uint8_t *__restrict__ slot_flag,
                                                             int32_t *__restrict__ out_nbr,
                                                             double *__restrict__ out_keys) {
   __shared__ WaveLds lds[kWavesPerBlock];
@@ -522,6 +552,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
     }
     const int64_t pend = min((task + 1) * kChunk, qv.n);
     for (int64_t p = task * kChunk; p < pend; ++p) {
+      if (slot_flag && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) == 0) continue;
       int64_t qi;
       if (qv.aligned) qi = __float_as_int(g.pts[p].w);
       else qi = qv.order ? qv.order[p] : p;
@@ -680,34 +711,110 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
 
       const double rad = support_r_h * cd.h;
       const double rad2 = rad * rad;
+      uint64_t mk = lane < ntop ? s.key[0] : kEmptyKey;
+      int32_t mi = lane < ntop ? s.idx[0] : 0x7fffffff;
+      int32_t mp = lane < ntop ? s.pos[0] : -1;
+      if (k > kfit || out_nbr || out_keys) sort_lanes(mk, mi, mp, lane);  // valid entries first
       const bool valid = lane < ntop;
-      const uint32_t m = popc(__ballot(valid && bitsd(s.key[0]) <= rad2));
+      const uint32_t m = popc(__ballot(valid && lane < kfit && bitsd(mk) <= rad2));
       // lists are stored per tile of 64 consecutive queries, neighbour-major:
-      // entry j of query p at [(p / 64) * 64 k + j * 64 + p % 64]
-      if (lane < k) nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = valid ? s.pos[0] : 0;
-      if (lane == 0) support[p] = (uint8_t)((finite && ntop == k) ? m : 0);
-      if (out_nbr || out_keys) {
-        // ascending (key, index) order for the caller: bitonic sort across lanes
-        uint64_t mk = valid ? s.key[0] : kEmptyKey;
-        int32_t mi = valid ? s.idx[0] : 0x7fffffff;
-        for (int size = 2; size <= 64; size <<= 1) {
-          for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint64_t ok = shfl_xor_u64(mk, stride);
-            const int32_t oi = __shfl_xor(mi, stride);
-            const bool up = (lane & size) == 0;
-            const bool lower = (lane & stride) == 0;
-            const bool olt = pair_lt(ok, oi, mk, mi);
-            const bool ogt = pair_lt(mk, mi, ok, oi);
-            const bool take = (lower == up) ? olt : ogt;
-            mk = take ? ok : mk;
-            mi = take ? oi : mi;
-          }
-        }
-        if (lane < k) {
-          if (out_nbr) out_nbr[qi * k + lane] = valid ? mi : -1;
-          if (out_keys) out_keys[qi * k + lane] = valid ? bitsd(mk) : bitsd(0x7ff8000000000000ull);
-        }
+      // entry j of query p at [(p / 64) * 64 k + j * 64 + p % 64]; entries
+      // past the cloud's size are -1
+      if (lane < k) nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = valid ? mp : -1;
+      const uint64_t kth = wave_max_u64(valid ? mk : 0ull);
+      if (lane == 0) {
+        support[p] = (uint8_t)((finite && ntop >= kfit) ? m : 0);
+        double *an = anchor + 4 * p;
+        an[0] = r[0]; an[1] = r[1]; an[2] = r[2];
+        an[3] = !finite ? -1.0 : (ntop < k ? __longlong_as_double(0x7ff0000000000000ll) : bitsd(kth));
       }
+      if (lane < kfit) {
+        if (out_nbr) out_nbr[qi * kfit + lane] = valid ? mi : -1;
+        if (out_keys) out_keys[qi * kfit + lane] = valid ? bitsd(mk) : bitsd(0x7ff8000000000000ull);
+      }
+    }
+  }
+}
+
+// Re-ranks the previous search's list of every slot for the slot's new
+// query. The list (k entries, positions) holds every point within
+// sqrt(bound) of the anchor, so a point outside it is at least
+// sqrt(bound) - |r - anchor| from the new query r (triangle inequality); when
+// the new kfit-th distance is below that, the kfit nearest are in the list
+// and the sorted list is final. Other slots are flagged for a fresh search.
+__global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, int32_t k,
+                                                     int32_t kfit, double support_r_h,
+                                                     int32_t *__restrict__ nbr,
+                                                     uint8_t *__restrict__ support,
+                                                     const double *__restrict__ anchor,
+                                                     uint8_t *__restrict__ slot_flag,
+                                                     int32_t *__restrict__ out_nbr,
+                                                     double *__restrict__ out_keys) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  for (int64_t task = blk * 4 + (threadIdx.x >> 6); task < nchunks;
+       task += (int64_t)gridDim.x * 4) {
+    const int64_t pend = min((task + 1) * kChunk, qv.n);
+    for (int64_t p = task * kChunk; p < pend; ++p) {
+      int64_t qi;
+      if (qv.aligned) qi = __float_as_int(g.pts[p].w);
+      else qi = qv.order ? qv.order[p] : p;
+      qi = __builtin_amdgcn_readfirstlane((int)qi);
+      double r[3];
+      if (qv.is_f64) {
+        const double *q = (const double *)qv.q + 3 * qi;
+        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+      } else {
+        const float *q = (const float *)qv.q + 3 * qi;
+        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+      }
+      const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
+      const double *an = anchor + 4 * p;
+      const double bound = an[3];
+      int32_t *row = nbr + (p >> 6) * 64 * k + (p & 63);
+      if (!finite) {
+        if (lane < k) row[lane * 64] = -1;
+        if (lane == 0) {
+          support[p] = 0;
+          slot_flag[p] = 0;
+        }
+        if (lane < kfit) {
+          if (out_nbr) out_nbr[qi * kfit + lane] = -1;
+          if (out_keys) out_keys[qi * kfit + lane] = bitsd(0x7ff8000000000000ull);
+        }
+        continue;
+      }
+      int32_t pos = lane < k ? row[lane * 64] : -1;
+      const bool have = pos >= 0 && (int64_t)pos < g.n_points;
+      const float4 P = g.pts[have ? pos : 0];
+      uint64_t mk = have ? dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]))
+                         : kEmptyKey;
+      int32_t mi = have ? __float_as_int(P.w) : 0x7fffffff;
+      int32_t mp = have ? pos : -1;
+      sort_lanes(mk, mi, mp, lane);
+      const uint32_t nvalid = popc(__ballot(mk != kEmptyKey));
+      const uint64_t kth = readlane_u64(mk, kfit - 1);
+      // certification (bound < 0: no usable list; +inf: the list is the cloud)
+      bool ok = bound >= 0.0 && nvalid >= (uint32_t)kfit;
+      if (ok && !isinf(bound)) {
+        const double dx = r[0] - an[0], dy = r[1] - an[1], dz = r[2] - an[2];
+        const double delta = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 0x1p-40);
+        const double reach = sqrt(bound) * (1.0 - 0x1p-40) - delta;
+        ok = reach > 0.0 && bitsd(kth) < reach * reach * (1.0 - 0x1p-40);
+      }
+      if (ok) {
+        const double rad = support_r_h * g.clouds[qv.qcloud ? qv.qcloud[qi] : 0].h;
+        const double rad2 = rad * rad;
+        const uint32_t m = popc(__ballot(lane < kfit && bitsd(mk) <= rad2));
+        if (lane < k) row[lane * 64] = mp;
+        if (lane < kfit) {
+          if (out_nbr) out_nbr[qi * kfit + lane] = mi;
+          if (out_keys) out_keys[qi * kfit + lane] = bitsd(mk);
+        }
+        if (lane == 0) support[p] = (uint8_t)m;
+      }
+      if (lane == 0) slot_flag[p] = ok ? 0 : 1;
     }
   }
 }
@@ -726,15 +833,21 @@ __global__ void k_fill_cloud_ids(const int64_t *__restrict__ offsets, int32_t n_
 
 }  // namespace
 
-hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, double support_r_h,
-                      int32_t *nbr, uint8_t *support, int32_t *out_nbr, double *out_keys,
+hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t kfit,
+                      double support_r_h, bool refresh, int32_t *nbr, uint8_t *support,
+                      double *anchor, uint8_t *flag, int32_t *out_nbr, double *out_keys,
                       hipStream_t s) {
   if (qv.n == 0) return hipSuccess;
   const int64_t tasks = (qv.n + kChunk - 1) / kChunk;
   int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 65536) blocks = 65536;
+  if (refresh) {
+    hipLaunchKernelGGL(k_knn_refresh, dim3((unsigned)blocks), dim3(256), 0, s, g, qv, k, kfit,
+                       support_r_h, nbr, support, anchor, flag, out_nbr, out_keys);
+  }
   hipLaunchKernelGGL(k_knn, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g, qv, k,
-                     support_r_h, nbr, support, out_nbr, out_keys);
+                     kfit, support_r_h, nbr, support, anchor, refresh ? flag : nullptr, out_nbr,
+                     out_keys);
   return hipGetLastError();
 }
 

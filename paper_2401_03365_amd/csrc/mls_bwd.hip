@@ -256,7 +256,7 @@ __device__ __forceinline__ void backward_one(const GridView &g, const QueryView 
   }
   const int cloud = qv.qcloud ? qv.qcloud[qi] : 0;
   const double h = g.clouds[cloud].h;
-  const int32_t *nb = nbr + (p >> 6) * 64 * k + (p & 63);
+  const int32_t *nb = nbr + (p >> 6) * 64 * qv.kstride + (p & 63);
 
   // statuses of the forward: support on canonical keys (counted during pass
   // 1), any invalid entry makes the query an outlier
@@ -406,20 +406,22 @@ __global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView q
   }
 }
 
-// Caller lists (original indices, row-major per query) -> sorted positions in
-// the tile layout; entries outside [0, n_points) become -1.
+// Caller lists (original indices, row-major per query, k each) -> sorted
+// positions in the tile layout (qv.kstride rows per tile); entries outside
+// [0, n_points) and rows past k become -1.
 __global__ void k_lists_from_caller(GridView g, QueryView qv, int32_t k,
                                     const int32_t *__restrict__ user,
                                     int32_t *__restrict__ nbr) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tiles = (qv.n + 63) / 64;
-  if (o >= tiles * 64 * (int64_t)k) return;
-  const int64_t tile = o / (64 * (int64_t)k);
-  const int64_t within = o - tile * 64 * (int64_t)k;
+  const int64_t ks = qv.kstride;
+  if (o >= tiles * 64 * ks) return;
+  const int64_t tile = o / (64 * ks);
+  const int64_t within = o - tile * 64 * ks;
   const int64_t p = tile * 64 + (within & 63);
   const int64_t j = within >> 6;
   int32_t pos = -1;
-  if (p < qv.n) {
+  if (p < qv.n && j < k) {
     const int64_t qi = query_of_slot(g, qv, p);
     const int32_t v = user[qi * k + j];
     if (v >= 0 && (int64_t)v < g.n_points) pos = g.inv_perm[v];
@@ -450,7 +452,7 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 hipError_t launch_lists_from_caller(const GridView &g, const QueryView &qv, int32_t k,
                                     const int32_t *user, int32_t *nbr, hipStream_t s) {
-  const int64_t total = (qv.n + 63) / 64 * 64 * (int64_t)k;
+  const int64_t total = (qv.n + 63) / 64 * 64 * (int64_t)qv.kstride;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_lists_from_caller, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, qv,
                      k, user, nbr);

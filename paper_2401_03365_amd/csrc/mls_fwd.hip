@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
   const int cloud = qv.qcloud ? qv.qcloud[qi] : 0;
   const double h = g.clouds[cloud].h;
   // neighbour j of query p: nb[j * 64] (tile layout of the search kernel)
-  const int32_t *nb = nbr + (p >> 6) * 64 * k + (p & 63);
+  const int32_t *nb = nbr + (p >> 6) * 64 * qv.kstride + (p & 63);
   const Rel<kF32> rel(r, 1.0 / h);
 
   double S0, S1[3], S2[6];

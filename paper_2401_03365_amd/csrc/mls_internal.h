@@ -173,10 +173,17 @@ struct QueryView {
   const int32_t *order;     // processing order -> query index, or null (identity)
   const int32_t *qcloud;    // per query cloud id, or null (cloud 0)
   int32_t aligned;          // queries aligned with points: order from the grid
+  int32_t kstride;          // entries per query in the tile lists (k + search extra)
 };
 
-hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, double support_r_h,
-                      int32_t *nbr_tiles, uint8_t *support, int32_t *out_nbr, double *out_keys,
+// Exact search of the k = qv.kstride nearest of every query into the tile
+// lists (the first kfit of each list are the kfit nearest), with the slot's
+// anchor and bound (4 doubles per slot) for later refreshes. With refresh,
+// the lists of the previous search are re-ranked for the new queries first
+// and only the slots they cannot certify (flag, 1 byte per slot) are searched.
+hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t kfit,
+                      double support_r_h, bool refresh, int32_t *nbr_tiles, uint8_t *support,
+                      double *anchor, uint8_t *flag, int32_t *out_nbr, double *out_keys,
                       hipStream_t s);
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               int32_t precision, int32_t min_support, const int32_t *nbr_tiles,

@@ -48,8 +48,8 @@ def check_sample(orc, P64, Qs, k, h, out, st, nbr, precision):
         assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
 
 
-def run_pass(g, q, k, precision, idx_t):
-    out, st, nbr = g.project(q, k, precision, return_neighbors=True)
+def run_pass(g, q, k, precision, idx_t, **kw):
+    out, st, nbr = g.project(q, k, precision, return_neighbors=True, **kw)
     torch.cuda.synchronize()
     return out, st, nbr[idx_t].cpu().numpy()
 

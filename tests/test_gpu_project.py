@@ -141,3 +141,64 @@ def test_statuses_on_gpu(orc):
     Q = np.array([[np.nan, 0, 0], [0.1, 0.1, np.inf]], dtype=np.float32)
     out, st = gpu_project(P, Q, 8, 0.1, "fp64")
     assert np.all(st == 3) and np.all(np.isnan(out))
+
+
+def test_iterated_passes_with_list_refresh(orc):
+    # passes 2 and 3 start from the 48 + 16 lists of the previous search:
+    # lists and outputs must match a fresh search (the oracle) in every pass
+    P = synth.heightfield(30000, sigma=1e-3, seed=34)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    cur = Pt.double()
+    P64 = P.astype(np.float64)
+    for it in range(3):
+        out, st, nbr = g.project(cur, 48, "fp32", return_neighbors=True, search_extra=16,
+                                 refresh=it > 0)
+        q = cur.cpu().numpy()
+        ref_nbr, _ = orc.knn(P64, q, 48)
+        np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
+        ref, ref_st = orc.project(P64, q, 48, h, nbr=ref_nbr)
+        np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
+        ok = (ref_st & 0x10) == 0
+        err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
+        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+        cur = out
+
+
+@pytest.mark.parametrize("shift_h", [0.05, 0.5, 3.0])
+def test_refresh_after_moves_is_exact(orc, shift_h):
+    # small moves are certified from the old lists, large ones searched
+    # afresh: either way the lists equal the oracle's
+    P = synth.torus(20000, sigma=0.005, n_outliers=200, seed=35)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    q0 = Pt.double()
+    g.project(q0, 32, "fp64", search_extra=8)
+    rng = np.random.default_rng(36)
+    q1 = q0.cpu().numpy() + rng.normal(size=P.shape) * shift_h * h
+    out, st, nbr = g.project(torch.from_numpy(q1).cuda(), 32, "fp64", return_neighbors=True,
+                             search_extra=8, refresh=True)
+    ref_nbr, _ = orc.knn(P.astype(np.float64), q1, 32)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
+    ref, ref_st = orc.project(P.astype(np.float64), q1, 32, h, nbr=ref_nbr)
+    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
+    assert err.max() <= FP64_MAX_H
+
+
+def test_search_extra_keeps_the_k_nearest_first(orc):
+    P = synth.sphere(20000, 0.01, seed=37)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    o1, s1, n1 = g.project(Pt.double(), 32, "fp64", return_neighbors=True)
+    o2, s2, n2 = g.project(Pt.double(), 32, "fp64", return_neighbors=True, search_extra=32)
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(s1, s2)
+    assert (o1 - o2).abs().max().item() <= 1e-12 * h
