@@ -7,7 +7,8 @@ k = 48, three iterated projection passes with the FP32-moment path.
 
 One step = build the grid of the cloud + 3 passes (each pass: exact kNN
 search, then moments / plane / quadratic fit / projection), inputs resident
-in HBM. value = 3 N / step time. The same steps are also timed with the FP64
+in HBM; the third pass refreshes the second pass's lists (exact, see
+MLS_STAGE_REFRESH). value = 3 N / step time. The same steps are also timed with the FP64
 path. Kernel durations come from HIP events recorded on the stream the
 library launches on; the CPU oracle is timed on a bounded sample of the same
 workload.
@@ -36,13 +37,14 @@ FP64_PEAK_TFLOPS = 78.6
 # projection): FP32 operations per neighbour (pass 1: 34, pass 2: 74; an
 # exponential counted as one operation each pass) plus the FP64 per-point
 # algebra (eigen-solve, frame, 6x6 Cholesky and solve: ~1,000 operations).
-# List refresh for later passes (MLS_STAGE_REFRESH): off. Measured on the 10M
-# height field, k = 48: the first pass moves the queries by 0.23 h (median),
-# so a refresh of pass 2 certifies only 59 % of the lists with 16 extra
-# neighbours, and a refresh of pass 3 from a 64-neighbour pass-2 search saves
-# only ~2 ms of 122 ms of search per step.
-SEARCH_EXTRA = 0
-REFRESH_FROM = 0
+# List refresh (MLS_STAGE_REFRESH) for the third pass: the second pass's
+# search keeps 16 neighbours beyond k, the third re-ranks them for the moved
+# queries and searches afresh only where the triangle inequality does not
+# certify the list (10 % of the queries on the 10M height field). The first
+# pass moves the queries by 0.23 h (median), too far for a refresh of pass 2
+# (59 % certified); the second moves them by 0.04 h.
+SEARCH_EXTRA = 16
+REFRESH_FROM = 2  # 0-based pass index of the first refreshed pass
 FIT_FLOPS_PER_NEIGHBOUR = 108 + 2
 FIT_FP64_FLOPS_PER_QUERY = 1000
 # Algorithmic work of the exact search per query: 200 candidate FP64 keys of
@@ -155,16 +157,17 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
         status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
         for p in range(passes):
             nxt = torch.empty_like(cur)
-            # with REFRESH_FROM > 0, the searches keep SEARCH_EXTRA more
-            # neighbours and the passes from REFRESH_FROM on refresh the lists
-            # of the pass before (exact; a fresh search where not certified)
+            # the pass before the first refreshed one keeps SEARCH_EXTRA more
+            # neighbours; refreshed passes re-rank the lists of the pass
+            # before (exact; a fresh search where not certified)
             refresh = 0 < REFRESH_FROM <= p
+            extra = SEARCH_EXTRA if 0 < REFRESH_FROM and p >= REFRESH_FROM - 1 else 0
             with ctx("refresh" if refresh else "search"):
                 grid.project(cur, k, precision, stages=1, out=nxt, status=status,
-                             search_extra=SEARCH_EXTRA, refresh=refresh)
+                             search_extra=extra, refresh=refresh)
             with ctx("fit"):
                 grid.project(cur, k, precision, stages=2, out=nxt, status=status,
-                             search_extra=SEARCH_EXTRA)
+                             search_extra=extra)
             if p == 0:
                 first = nxt
             cur = nxt

@@ -553,6 +553,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
     const int64_t pend = min((task + 1) * kChunk, qv.n);
     for (int64_t p = task * kChunk; p < pend; ++p) {
       if (slot_flag && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) == 0) continue;
+      if (slot_flag) {
+        // the refresh left the squared kfit-th distance of the old list
+        const double hint = anchor[4 * p + 3];
+        if (hint > 0.0 && isfinite(hint)) rho_est = sqrt(hint);
+      }
       int64_t qi;
       if (qv.aligned) qi = __float_as_int(g.pts[p].w);
       else qi = qv.order ? qv.order[p] : p;
@@ -736,6 +741,74 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
   }
 }
 
+// Refresh without re-ranking, one lane per slot: when the first kfit entries
+// of the previous list are still the kfit nearest of the list for the new
+// query (their largest (key, index) pair is below the smallest of the other
+// entries) and the certification of the re-ranked refresh holds, the list is
+// final as it stands; only the support count is rewritten. Slots where this
+// does not hold are flagged 2 for the re-ranking refresh.
+__global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView qv, int32_t k,
+                                                          int32_t kfit, double support_r_h,
+                                                          const int32_t *__restrict__ nbr,
+                                                          uint8_t *__restrict__ support,
+                                                          const double *__restrict__ anchor,
+                                                          uint8_t *__restrict__ slot_flag) {
+  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (p >= qv.n) return;
+  int64_t qi;
+  if (qv.aligned) qi = __float_as_int(g.pts[p].w);
+  else qi = qv.order ? qv.order[p] : p;
+  double r[3];
+  if (qv.is_f64) {
+    const double *q = (const double *)qv.q + 3 * qi;
+    r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+  } else {
+    const float *q = (const float *)qv.q + 3 * qi;
+    r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+  }
+  const double *an = anchor + 4 * p;
+  const double bound = an[3];
+  const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
+  if (!finite || !(bound >= 0.0)) {
+    slot_flag[p] = 2;
+    return;
+  }
+  const double rad = support_r_h * g.clouds[qv.qcloud ? qv.qcloud[qi] : 0].h;
+  const double rad2 = rad * rad;
+  const int32_t *row = nbr + (p >> 6) * 64 * k + (p & 63);
+  uint64_t in_k = 0ull, out_k = kEmptyKey;  // largest pair inside, smallest outside
+  int32_t in_i = -1, out_i = 0x7fffffff;
+  int m = 0;
+  bool valid = true;
+  for (int j = 0; j < k; ++j) {
+    const int32_t pos = row[j * 64];
+    const bool have = pos >= 0 && (int64_t)pos < g.n_points;
+    const float4 P = g.pts[have ? pos : 0];
+    const uint64_t key = dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]));
+    const int32_t idx = __float_as_int(P.w);
+    if (j < kfit) {
+      valid = valid && have;
+      const bool gt = pair_lt(in_k, in_i, key, idx);
+      in_k = gt ? key : in_k;
+      in_i = gt ? idx : in_i;
+      m += (have && bitsd(key) <= rad2) ? 1 : 0;
+    } else if (have) {
+      const bool lt = pair_lt(key, idx, out_k, out_i);
+      out_k = lt ? key : out_k;
+      out_i = lt ? idx : out_i;
+    }
+  }
+  bool ok = valid && pair_lt(in_k, in_i, out_k, out_i);
+  if (ok && !isinf(bound)) {
+    const double dx = r[0] - an[0], dy = r[1] - an[1], dz = r[2] - an[2];
+    const double delta = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 0x1p-40);
+    const double reach = sqrt(bound) * (1.0 - 0x1p-40) - delta;
+    ok = reach > 0.0 && bitsd(in_k) < reach * reach * (1.0 - 0x1p-40);
+  }
+  if (ok) support[p] = (uint8_t)m;
+  slot_flag[p] = ok ? 0 : 2;
+}
+
 // Re-ranks the previous search's list of every slot for the slot's new
 // query. The list (k entries, positions) holds every point within
 // sqrt(bound) of the anchor, so a point outside it is at least
@@ -746,8 +819,9 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
                                                      int32_t kfit, double support_r_h,
                                                      int32_t *__restrict__ nbr,
                                                      uint8_t *__restrict__ support,
-                                                     const double *__restrict__ anchor,
+                                                     double *__restrict__ anchor,
                                                      uint8_t *__restrict__ slot_flag,
+                                                     bool pending_only,
                                                      int32_t *__restrict__ out_nbr,
                                                      double *__restrict__ out_keys) {
   const int lane = threadIdx.x & 63;
@@ -757,6 +831,7 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
        task += (int64_t)gridDim.x * 4) {
     const int64_t pend = min((task + 1) * kChunk, qv.n);
     for (int64_t p = task * kChunk; p < pend; ++p) {
+      if (pending_only && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) != 2) continue;
       int64_t qi;
       if (qv.aligned) qi = __float_as_int(g.pts[p].w);
       else qi = qv.order ? qv.order[p] : p;
@@ -814,7 +889,15 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
         }
         if (lane == 0) support[p] = (uint8_t)m;
       }
-      if (lane == 0) slot_flag[p] = ok ? 0 : 1;
+      const uint64_t klast = readlane_u64(mk, k - 1);
+      if (lane == 0) {
+        slot_flag[p] = ok ? 0 : 1;
+        // a slot left to the fresh search keeps, in place of its bound, the
+        // squared distance of the list's last entry for the new query: its k
+        // nearest lie within it, so the search can pick a block that
+        // certifies at once
+        if (!ok) anchor[4 * p + 3] = nvalid == (uint32_t)k ? bitsd(klast) : 0.0;
+      }
     }
   }
 }
@@ -842,8 +925,14 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
   int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 65536) blocks = 65536;
   if (refresh) {
+    // lists that need no re-ranking are settled one lane per slot; sorted
+    // output for the caller takes the re-ranking path for every slot
+    const bool lane_pass = !out_nbr && !out_keys;
+    if (lane_pass)
+      hipLaunchKernelGGL(k_knn_refresh_lane, dim3((unsigned)((qv.n + 255) / 256)), dim3(256), 0,
+                         s, g, qv, k, kfit, support_r_h, nbr, support, anchor, flag);
     hipLaunchKernelGGL(k_knn_refresh, dim3((unsigned)blocks), dim3(256), 0, s, g, qv, k, kfit,
-                       support_r_h, nbr, support, anchor, flag, out_nbr, out_keys);
+                       support_r_h, nbr, support, anchor, flag, lane_pass, out_nbr, out_keys);
   }
   hipLaunchKernelGGL(k_knn, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g, qv, k,
                      kfit, support_r_h, nbr, support, anchor, refresh ? flag : nullptr, out_nbr,

@@ -73,6 +73,20 @@ def test_torus_1m_with_outliers(orc, precision):
     assert ((st[idx_t[400:]] & 0x0F) == 1).sum().item() > 50  # most outliers flagged
 
 
+def sampled_tile_sets(g, k_list, kfit, qidx):
+    """Sorted original indices of the first kfit entries of the sampled
+    queries' lists in the projection workspace (queries aligned with the
+    points; the lists lead the workspace in tiles of 64 slots)."""
+    spts, inv = g.sorted_points()
+    n = spts.shape[0]
+    tiles = (n + 63) // 64
+    raw = g._proj_ws[: 4 * tiles * 64 * k_list].view(torch.int32).view(tiles, k_list, 64)
+    slots = inv[qidx].long()
+    pos = raw[slots >> 6, :kfit, :].gather(2, (slots & 63).view(-1, 1, 1).expand(-1, kfit, 1))
+    orig = spts[:, 3].contiguous().view(torch.int32).long()
+    return torch.sort(orig[pos.view(-1, kfit).long()], dim=1).values.cpu().numpy()
+
+
 def test_heightfield_10m_three_passes(orc):
     P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
     h = synth.mean_nn_h(P)
@@ -85,9 +99,16 @@ def test_heightfield_10m_three_passes(orc):
     P64 = P.astype(np.float64)
     cur = Pt.double()
     for it in range(3):
-        out, st, nbr = run_pass(g, cur, 48, "fp32", idx_t)
-        check_sample(orc, P64, cur[idx_t].cpu().numpy(), 48, h, out[idx_t].cpu().numpy(),
-                     st[idx_t].cpu().numpy(), nbr, "fp32")
+        # as timed: the second search keeps 16 more, the third pass refreshes
+        extra = 16 if it > 0 else 0
+        out, st = g.project(cur, 48, "fp32", search_extra=extra, refresh=it == 2)
+        torch.cuda.synchronize()
+        sets = sampled_tile_sets(g, 48 + extra, 48, idx_t)
+        qs = cur[idx_t].cpu().numpy()
+        ref_nbr, _ = orc.knn(P64, qs, 48)
+        np.testing.assert_array_equal(sets, np.sort(ref_nbr, axis=1))
+        check_sample(orc, P64, qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
+                     ref_nbr, "fp32")
         cur = out
 
 

@@ -202,3 +202,44 @@ def test_search_extra_keeps_the_k_nearest_first(orc):
     torch.cuda.synchronize()
     assert torch.equal(n1, n2) and torch.equal(s1, s2)
     assert (o1 - o2).abs().max().item() <= 1e-12 * h
+
+
+def tile_lists(g, n, k_list, kfit):
+    """The first kfit entries of every slot's list in the projection
+    workspace (the lists lead the workspace: tiles of 64 slots, k_list rows
+    of 64 sorted positions), as sorted rows of original indices per query."""
+    tiles = (n + 63) // 64
+    raw = g._proj_ws[: 4 * tiles * 64 * k_list].view(torch.int32).view(tiles, k_list, 64)
+    pos = raw[:, :kfit, :].permute(0, 2, 1).reshape(tiles * 64, kfit)[:n].long()
+    spts, _ = g.sorted_points()
+    orig = spts[:, 3].contiguous().view(torch.int32).long()
+    lists = orig[pos]                      # slot -> original indices
+    q_of_slot = orig[:n]                   # aligned queries: slot p is sorted point p
+    out = torch.empty_like(lists)
+    out[q_of_slot] = lists
+    return torch.sort(out, dim=1).values.cpu().numpy()
+
+
+def test_refresh_without_reranking_keeps_exact_sets(orc):
+    # passes 1-2 fresh (64 kept), pass 3 refreshed: most lists are settled
+    # one lane per slot without re-ranking; every set must equal the oracle's
+    P = synth.heightfield(30000, sigma=1e-3, seed=38)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    P64 = P.astype(np.float64)
+    cur = Pt.double()
+    for it in range(3):
+        out, st = g.project(cur, 48, "fp32", search_extra=16, refresh=it == 2)
+        torch.cuda.synchronize()
+        got = tile_lists(g, P.shape[0], 64, 48)
+        q = cur.cpu().numpy()
+        ref_nbr, _ = orc.knn(P64, q, 48)
+        np.testing.assert_array_equal(got, np.sort(ref_nbr, axis=1))
+        ref, ref_st = orc.project(P64, q, 48, h, nbr=ref_nbr)
+        np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
+        ok = (ref_st & 0x10) == 0
+        err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
+        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+        cur = out
