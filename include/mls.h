@@ -110,7 +110,8 @@ typedef struct {
  * for (R = its last entry's distance), so when the new k-th distance is below
  * R minus the query's displacement, the k nearest are in the list (triangle
  * inequality) and the re-ranked list is the exact result; every other query
- * is searched afresh. The result is the same as a fresh search. */
+ * is searched afresh (every query when the previous search kept no extra
+ * entries, search_extra = 0). The result is the same as a fresh search. */
 typedef enum {
   MLS_STAGE_ALL = 0,
   MLS_STAGE_SEARCH = 1,

@@ -517,7 +517,8 @@ __constant__ int8_t kOptHalf[2 * kMaxLevels] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1,
 // the caller's lists cover the first kfit. The slot's anchor (the query) and
 // bound (the k-th key: every point outside the list is at least that far, in
 // squared distance, from the anchor; +inf when the list holds the whole
-// cloud, -1 for a non-finite query) serve later refreshes.
+// cloud; -1 for a non-finite query or a list without extra entries, which a
+// refresh then searches afresh) serve later refreshes.
 __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
                                                             int32_t kfit, double support_r_h,
                                                             int32_t *__restrict__ nbr,
@@ -726,12 +727,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       // entry j of query p at [(p / 64) * 64 k + j * 64 + p % 64]; entries
       // past the cloud's size are -1
       if (lane < k) nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = valid ? mp : -1;
-      const uint64_t kth = wave_max_u64(valid ? mk : 0ull);
+      // the list is sorted when it keeps extra entries: its k-th key is in
+      // lane k - 1
+      const uint64_t kth = k > kfit ? readlane_u64(mk, k - 1) : 0ull;
       if (lane == 0) {
         support[p] = (uint8_t)((finite && ntop >= kfit) ? m : 0);
         double *an = anchor + 4 * p;
         an[0] = r[0]; an[1] = r[1]; an[2] = r[2];
-        an[3] = !finite ? -1.0 : (ntop < k ? __longlong_as_double(0x7ff0000000000000ll) : bitsd(kth));
+        an[3] = (!finite || k == kfit) ? -1.0
+                : (ntop < k ? __longlong_as_double(0x7ff0000000000000ll) : bitsd(kth));
       }
       if (lane < kfit) {
         if (out_nbr) out_nbr[qi * kfit + lane] = valid ? mi : -1;
@@ -741,15 +745,51 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
   }
 }
 
-// Refresh without re-ranking, one lane per slot: when the first kfit entries
-// of the previous list are still the kfit nearest of the list for the new
-// query (their largest (key, index) pair is below the smallest of the other
-// entries) and the certification of the re-ranked refresh holds, the list is
-// final as it stands; only the support count is rewritten. Slots where this
-// does not hold are flagged 2 for the re-ranking refresh.
+// Refresh with few changes, one lane per slot. The first kfit entries of a
+// list are the kfit nearest of the list for the query it was searched for;
+// for the moved query only entries near the kfit-th distance can change
+// sides. The lane keeps the kSwap largest (key, index) pairs among the first
+// kfit and the kSwap smallest among the others; when fewer than kSwap pairs
+// are out of order, swapping them gives the kfit nearest of the list, and
+// with the certification of the re-ranking refresh the list is final (only
+// the swapped rows and the support count are rewritten). Other slots are
+// flagged 2 for the re-ranking refresh.
+constexpr int kSwap = 4;
+
+// kSwap (key, index, row, position) entries held in registers (one array
+// per field, so that every access is static after unrolling).
+struct Ents {
+  uint64_t key[kSwap];
+  int32_t idx[kSwap], row[kSwap], pos[kSwap];
+};
+
+// Inserts e into the ordered entries, dropping the last: descending when
+// `desc` (largest first), else ascending. Branch-free selects.
+template <bool desc>
+__device__ __forceinline__ void ents_insert(Ents &a, uint64_t ek, int32_t ei, int32_t er,
+                                            int32_t ep) {
+  bool c[kSwap];
+#pragma unroll
+  for (int i = 0; i < kSwap; ++i)
+    c[i] = desc ? pair_lt(a.key[i], a.idx[i], ek, ei) : pair_lt(ek, ei, a.key[i], a.idx[i]);
+#pragma unroll
+  for (int i = kSwap - 1; i > 0; --i) {
+    const bool from_prev = c[i] && c[i - 1];
+    const bool here = c[i] && !c[i - 1];
+    a.key[i] = from_prev ? a.key[i - 1] : (here ? ek : a.key[i]);
+    a.idx[i] = from_prev ? a.idx[i - 1] : (here ? ei : a.idx[i]);
+    a.row[i] = from_prev ? a.row[i - 1] : (here ? er : a.row[i]);
+    a.pos[i] = from_prev ? a.pos[i - 1] : (here ? ep : a.pos[i]);
+  }
+  a.key[0] = c[0] ? ek : a.key[0];
+  a.idx[0] = c[0] ? ei : a.idx[0];
+  a.row[0] = c[0] ? er : a.row[0];
+  a.pos[0] = c[0] ? ep : a.pos[0];
+}
+
 __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView qv, int32_t k,
                                                           int32_t kfit, double support_r_h,
-                                                          const int32_t *__restrict__ nbr,
+                                                          int32_t *__restrict__ nbr,
                                                           uint8_t *__restrict__ support,
                                                           const double *__restrict__ anchor,
                                                           uint8_t *__restrict__ slot_flag) {
@@ -769,15 +809,19 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
   const double *an = anchor + 4 * p;
   const double bound = an[3];
   const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
-  if (!finite || !(bound >= 0.0)) {
+  if (!finite || !(bound >= 0.0) || kfit < kSwap) {
     slot_flag[p] = 2;
     return;
   }
   const double rad = support_r_h * g.clouds[qv.qcloud ? qv.qcloud[qi] : 0].h;
   const double rad2 = rad * rad;
-  const int32_t *row = nbr + (p >> 6) * 64 * k + (p & 63);
-  uint64_t in_k = 0ull, out_k = kEmptyKey;  // largest pair inside, smallest outside
-  int32_t in_i = -1, out_i = 0x7fffffff;
+  int32_t *row = nbr + (p >> 6) * 64 * k + (p & 63);
+  Ents hi, lo;  // hi descending (largest first), lo ascending
+#pragma unroll
+  for (int i = 0; i < kSwap; ++i) {
+    hi.key[i] = 0ull; hi.idx[i] = -1; hi.row[i] = 0; hi.pos[i] = 0;
+    lo.key[i] = kEmptyKey; lo.idx[i] = 0x7fffffff; lo.row[i] = 0; lo.pos[i] = 0;
+  }
   int m = 0;
   bool valid = true;
   for (int j = 0; j < k; ++j) {
@@ -788,24 +832,49 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
     const int32_t idx = __float_as_int(P.w);
     if (j < kfit) {
       valid = valid && have;
-      const bool gt = pair_lt(in_k, in_i, key, idx);
-      in_k = gt ? key : in_k;
-      in_i = gt ? idx : in_i;
       m += (have && bitsd(key) <= rad2) ? 1 : 0;
+      ents_insert<true>(hi, key, idx, j, pos);
     } else if (have) {
-      const bool lt = pair_lt(key, idx, out_k, out_i);
-      out_k = lt ? key : out_k;
-      out_i = lt ? idx : out_i;
+      ents_insert<false>(lo, key, idx, j, pos);
     }
   }
-  bool ok = valid && pair_lt(in_k, in_i, out_k, out_i);
+  // pairs out of order: lo[i] < hi[i] holds for i < s (both sides monotone)
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kSwap; ++i) s += pair_lt(lo.key[i], lo.idx[i], hi.key[i], hi.idx[i]) ? 1 : 0;
+  bool ok = valid && s < kSwap;
+  // the kfit-th pair after the swaps: the larger of the largest kept inside
+  // entry and the largest entry swapped in
+  uint64_t kk = hi.key[0];
+  int32_t ki = hi.idx[0];
+#pragma unroll
+  for (int i = 1; i < kSwap; ++i) {
+    kk = (s == i) ? hi.key[i] : kk;
+    ki = (s == i) ? hi.idx[i] : ki;
+  }
+#pragma unroll
+  for (int i = 0; i < kSwap; ++i) {
+    const bool up = i == s - 1 && pair_lt(kk, ki, lo.key[i], lo.idx[i]);
+    kk = up ? lo.key[i] : kk;
+    ki = up ? lo.idx[i] : ki;
+  }
   if (ok && !isinf(bound)) {
     const double dx = r[0] - an[0], dy = r[1] - an[1], dz = r[2] - an[2];
     const double delta = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 0x1p-40);
     const double reach = sqrt(bound) * (1.0 - 0x1p-40) - delta;
-    ok = reach > 0.0 && bitsd(in_k) < reach * reach * (1.0 - 0x1p-40);
+    ok = reach > 0.0 && bitsd(kk) < reach * reach * (1.0 - 0x1p-40);
   }
-  if (ok) support[p] = (uint8_t)m;
+  if (ok) {
+#pragma unroll
+    for (int i = 0; i < kSwap; ++i) {
+      if (i < s) {
+        row[hi.row[i] * 64] = lo.pos[i];
+        row[lo.row[i] * 64] = hi.pos[i];
+        m += (bitsd(lo.key[i]) <= rad2 ? 1 : 0) - (bitsd(hi.key[i]) <= rad2 ? 1 : 0);
+      }
+    }
+    support[p] = (uint8_t)m;
+  }
   slot_flag[p] = ok ? 0 : 2;
 }
 

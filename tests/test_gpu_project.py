@@ -191,6 +191,31 @@ def test_refresh_after_moves_is_exact(orc, shift_h):
     assert err.max() <= FP64_MAX_H
 
 
+def test_refresh_after_search_without_extras_is_exact(orc):
+    # a search that keeps no extra entries leaves no bound (even over the
+    # bounds of an earlier search with extras): the refresh searches afresh
+    P = synth.torus(20000, sigma=0.005, n_outliers=200, seed=39)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    q0 = Pt.double()
+    g.project(q0, 32, "fp64", search_extra=8)
+    rng = np.random.default_rng(40)
+    q1 = q0.cpu().numpy() + rng.normal(size=P.shape) * 0.5 * h
+    g.project(torch.from_numpy(q1).cuda(), 32, "fp64")
+    q2 = q1 + rng.normal(size=P.shape) * 0.05 * h
+    out, st, nbr = g.project(torch.from_numpy(q2).cuda(), 32, "fp64", return_neighbors=True,
+                             refresh=True)
+    ref_nbr, _ = orc.knn(P.astype(np.float64), q2, 32)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
+    ref, ref_st = orc.project(P.astype(np.float64), q2, 32, h, nbr=ref_nbr)
+    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
+    assert err.max() <= FP64_MAX_H
+
+
 def test_search_extra_keeps_the_k_nearest_first(orc):
     P = synth.sphere(20000, 0.01, seed=37)
     h = synth.mean_nn_h(P)
