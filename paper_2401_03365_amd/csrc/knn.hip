@@ -44,6 +44,13 @@ constexpr int kNew = (kSlots - 1) * 64;   // candidates per batch
 constexpr int kMaxRing = 12;
 constexpr int kChunk = 64;                // consecutive queries per wave task
 
+// The queries of a wave's chunk, loaded together at the chunk's start.
+struct alignas(16) ChunkQueries {
+  double x[kChunk], y[kChunk], z[kChunk];
+  int32_t qi[kChunk];
+  int32_t cloud[kChunk];
+};
+
 struct alignas(16) WaveLds {
   uint32_t cstart[128];
   uint32_t cexcl[128];
@@ -68,8 +75,53 @@ __device__ __forceinline__ bool pair_lt(uint64_t ka, int32_t ia, uint64_t kb, in
 
 __device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  return (uint64_t)__shfl_xor((long long)v, m);
+// Cross-lane moves on the DPP and permlane paths of the VALU (no LDS round
+// trip). dpp<ctrl, rows>: lanes whose source is outside their row, or whose
+// row is masked off, get `fill`.
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowShl4 = 0x104, kRowRor8 = 0x128, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;  // quad_perm [1,0,3,2], [2,3,0,1]
+
+template <int ctrl, int rows = 0xf>
+__device__ __forceinline__ uint32_t dpp(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, ctrl, rows, 0xf, false);
+}
+
+// Value of lane ^ s (s a power of two up to 32, known at compile time once
+// unrolled).
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int s, int lane) {
+  switch (s) {
+    case 1: return dpp<kQuadXor1>(v, v);
+    case 2: return dpp<kQuadXor2>(v, v);
+    case 4: {
+      const uint32_t up = dpp<kRowShl4>(v, v), down = dpp<kRowShr4>(v, v);
+      return (lane & 4) ? down : up;
+    }
+    case 8: return dpp<kRowRor8>(v, v);
+    case 16: {
+      const auto q = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+      return (lane & 16) ? q[0] : q[1];
+    }
+    default: {
+      const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+      return (lane & 32) ? q[0] : q[1];
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v, int s, int lane) {
+  return ((uint64_t)xor_lane((uint32_t)(v >> 32), s, lane) << 32) | xor_lane((uint32_t)v, s, lane);
+}
+
+// Inclusive prefix sum over the wave's lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  x += dpp<kRowShr1>(x, 0u);
+  x += dpp<kRowShr2>(x, 0u);
+  x += dpp<kRowShr4>(x, 0u);
+  x += dpp<kRowShr8>(x, 0u);
+  x += dpp<kRowBcast15, 0xa>(x, 0u);
+  x += dpp<kRowBcast31, 0xc>(x, 0u);
+  return x;
 }
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
@@ -77,12 +129,30 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
 }
 
+// A wave-uniform double held in scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int ctrl, int rows = 0xf>
+__device__ __forceinline__ uint64_t max_step(uint64_t v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  const uint64_t o = ((uint64_t)dpp<ctrl, rows>(hi, hi) << 32) | dpp<ctrl, rows>(lo, lo);
+  return o > v ? o : v;
+}
+
+// Maximum over the wave (inclusive max-scan; lane 63 holds the maximum).
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t o = shfl_xor_u64(v, off);
-    v = o > v ? o : v;
-  }
-  return v;
+  v = max_step<kRowShr1>(v);
+  v = max_step<kRowShr2>(v);
+  v = max_step<kRowShr4>(v);
+  v = max_step<kRowShr8>(v);
+  v = max_step<kRowBcast15, 0xa>(v);
+  v = max_step<kRowBcast31, 0xc>(v);
+  return readlane_u64(v, 63);
 }
 
 struct Slots {
@@ -172,11 +242,7 @@ __device__ int select_topk(const Slots &s, int k, double scale, WaveLds &L, int 
   wave_sync();
   const uint4 hv = reinterpret_cast<const uint4 *>(L.hist)[lane];
   const uint32_t s4 = hv.x + hv.y + hv.z + hv.w;
-  uint32_t incl = s4;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
-    incl += (lane >= off) ? y : 0u;
-  }
+  const uint32_t incl = wave_incl_scan(s4);
   const uint32_t e0 = incl - s4, e1 = e0 + hv.x, e2 = e1 + hv.y, e3 = e2 + hv.z;
   const uint32_t ku = (uint32_t)k;
   int mybin = -1;
@@ -260,11 +326,13 @@ __device__ int compact(Slots &s, const bool keep[kSlots], WaveLds &L, int lane) 
 // Sorts the (key, index, position) triples held one per lane ascending by
 // (key, index) across the wave (bitonic network over 64 lanes).
 __device__ __forceinline__ void sort_lanes(uint64_t &mk, int32_t &mi, int32_t &mp, int lane) {
+#pragma unroll
   for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const uint64_t ok = shfl_xor_u64(mk, stride);
-      const int32_t oi = __shfl_xor(mi, stride);
-      const int32_t op = __shfl_xor(mp, stride);
+      const uint64_t ok = xor_lane_u64(mk, stride, lane);
+      const int32_t oi = (int32_t)xor_lane((uint32_t)mi, stride, lane);
+      const int32_t op = (int32_t)xor_lane((uint32_t)mp, stride, lane);
       const bool up = (lane & size) == 0;
       const bool lower = (lane & stride) == 0;
       const bool olt = pair_lt(ok, oi, mk, mi);
@@ -277,19 +345,28 @@ __device__ __forceinline__ void sort_lanes(uint64_t &mk, int32_t &mi, int32_t &m
   }
 }
 
-// Largest (key, index) pair of the running top-k.
+template <int ctrl, int rows = 0xf>
+__device__ __forceinline__ void pair_max_step(uint64_t &mk, int32_t &mi) {
+  const uint32_t lo = (uint32_t)mk, hi = (uint32_t)(mk >> 32);
+  const uint64_t ok = ((uint64_t)dpp<ctrl, rows>(hi, hi) << 32) | dpp<ctrl, rows>(lo, lo);
+  const int32_t oi = (int32_t)dpp<ctrl, rows>((uint32_t)mi, (uint32_t)mi);
+  const bool t = pair_lt(mk, mi, ok, oi);
+  mk = t ? ok : mk;
+  mi = t ? oi : mi;
+}
+
+// Largest (key, index) pair of the running top-k (uniform result).
 __device__ void top_max(const Slots &s, int ntop, int lane, uint64_t &kmax, int32_t &imax) {
   uint64_t mk = lane < ntop ? s.key[0] : 0;
   int32_t mi = lane < ntop ? s.idx[0] : -1;
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t ok = shfl_xor_u64(mk, off);
-    const int32_t oi = __shfl_xor(mi, off);
-    const bool t = pair_lt(mk, mi, ok, oi);
-    mk = t ? ok : mk;
-    mi = t ? oi : mi;
-  }
-  kmax = mk;
-  imax = mi;
+  pair_max_step<kRowShr1>(mk, mi);
+  pair_max_step<kRowShr2>(mk, mi);
+  pair_max_step<kRowShr4>(mk, mi);
+  pair_max_step<kRowShr8>(mk, mi);
+  pair_max_step<kRowBcast15, 0xa>(mk, mi);
+  pair_max_step<kRowBcast31, 0xc>(mk, mi);
+  kmax = readlane_u64(mk, 63);
+  imax = __builtin_amdgcn_readlane(mi, 63);
 }
 
 // Distance from r to the boundary of the box of cells [c0 - L, c0 + L]
@@ -339,21 +416,13 @@ __device__ __forceinline__ int2 lookup_if(const GridView &g, int cloud, const Cl
   return make_int2(0, 0);
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = (uint32_t)__shfl_up((int)x, off);
-    x += (lane >= off) ? y : 0u;
-  }
-  return x;
-}
-
 // Stages up to 128 cell ranges (entry lane and entry 64 + lane) and their
 // exclusive prefix in LDS; returns the candidate total.
 __device__ __forceinline__ int32_t stage_ranges(int2 a, int2 b, WaveLds &L, int lane) {
-  const uint32_t xa = wave_incl_scan((uint32_t)a.y, lane);
-  const uint32_t ta = (uint32_t)__shfl((int)xa, 63);
-  const uint32_t xb = wave_incl_scan((uint32_t)b.y, lane);
-  const uint32_t tb = (uint32_t)__shfl((int)xb, 63);
+  const uint32_t xa = wave_incl_scan((uint32_t)a.y);
+  const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int)xa, 63);
+  const uint32_t xb = wave_incl_scan((uint32_t)b.y);
+  const uint32_t tb = (uint32_t)__builtin_amdgcn_readlane((int)xb, 63);
   wave_sync();
   L.cstart[lane] = (uint32_t)a.x;
   L.cexcl[lane] = xa - (uint32_t)a.y;
@@ -504,11 +573,9 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
   return ntop;
 }
 
-// Block options (level, half-width), in increasing block volume
-// ((2 half + 1) 2^level)^3: each guarantees a clearance of about half * 2^level
-// cells of the finest level.
-__constant__ int8_t kOptLevel[2 * kMaxLevels] = {0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 5, 5, 6, 6, 7, 7};
-__constant__ int8_t kOptHalf[2 * kMaxLevels] = {1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
+// Block options o = 0 .. 2 levels - 1: level o / 2, half-width 1 + o % 2, in
+// increasing block volume ((2 half + 1) 2^level)^3; each guarantees a
+// clearance of about half * 2^level cells of the finest level.
 
 // Searches the k (= kfit + extra) nearest of every query slot (only the
 // slots flagged in slot_flag when it is given). The tile list of a slot holds
@@ -528,9 +595,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
                                                             int32_t *__restrict__ out_nbr,
                                                             double *__restrict__ out_keys) {
   __shared__ WaveLds lds[kWavesPerBlock];
+  __shared__ ChunkQueries chq[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   WaveLds &L = lds[wv];
+  ChunkQueries &Q = chq[wv];
   const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
   const int nopt = 2 * g.n_levels;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -551,27 +620,42 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       s.key[i] = kEmptyKey; s.pos[i] = 0; s.idx[i] = 0x7fffffff;
       cx[i] = cy[i] = cz[i] = 0.f;
     }
-    const int64_t pend = min((task + 1) * kChunk, qv.n);
-    for (int64_t p = task * kChunk; p < pend; ++p) {
+    const int64_t p0 = task * kChunk;
+    const int64_t pend = min(p0 + kChunk, qv.n);
+    {
+      // lane j loads query slot p0 + j (one round trip for the chunk)
+      const int64_t p = p0 + lane;
+      int32_t qi = 0, cl = 0;
+      double x = 0.0, y = 0.0, z = 0.0;
+      if (p < pend) {
+        if (qv.aligned) qi = __float_as_int(g.pts[p].w);
+        else qi = qv.order ? qv.order[p] : (int32_t)p;
+        if (qv.is_f64) {
+          const double *q = (const double *)qv.q + 3 * (int64_t)qi;
+          x = q[0]; y = q[1]; z = q[2];
+        } else {
+          const float *q = (const float *)qv.q + 3 * (int64_t)qi;
+          x = q[0]; y = q[1]; z = q[2];
+        }
+        cl = qv.qcloud ? qv.qcloud[qi] : 0;
+      }
+      wave_sync();
+      Q.x[lane] = x; Q.y[lane] = y; Q.z[lane] = z;
+      Q.qi[lane] = qi;
+      Q.cloud[lane] = cl;
+      wave_sync();
+    }
+    for (int64_t p = p0; p < pend; ++p) {
       if (slot_flag && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) == 0) continue;
       if (slot_flag) {
         // the refresh left the squared kfit-th distance of the old list
         const double hint = anchor[4 * p + 3];
         if (hint > 0.0 && isfinite(hint)) rho_est = sqrt(hint);
       }
-      int64_t qi;
-      if (qv.aligned) qi = __float_as_int(g.pts[p].w);
-      else qi = qv.order ? qv.order[p] : p;
-      qi = __builtin_amdgcn_readfirstlane((int)qi);
-      double r[3];
-      if (qv.is_f64) {
-        const double *q = (const double *)qv.q + 3 * qi;
-        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
-      } else {
-        const float *q = (const float *)qv.q + 3 * qi;
-        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
-      }
-      const int cloud = __builtin_amdgcn_readfirstlane(qv.qcloud ? qv.qcloud[qi] : 0);
+      const int j = (int)(p - p0);
+      const int64_t qi = __builtin_amdgcn_readfirstlane(Q.qi[j]);
+      const double r[3] = {uniform_f64(Q.x[j]), uniform_f64(Q.y[j]), uniform_f64(Q.z[j])};
+      const int cloud = __builtin_amdgcn_readfirstlane(Q.cloud[j]);
       const CloudDev &cd = g.clouds[cloud];
       const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
       int ntop = 0;
@@ -588,22 +672,30 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
         bool solved = false;
         if (lmin == 0) {
           double target = 1.05 * rho_est;
+          // the query's offset in its level-0 cell, in cell units (FP32: it
+          // only steers the choice of block, never the certification)
+          float u[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            u[a] = (float)((r[a] - cd.origin[a]) * cd.inv_cell - (double)c0[a]);
           for (int att = 0; att < 2 * kMaxLevels + 2 && !solved; ++att) {
             // smallest block whose clearance (half-width plus the query's
-            // interior clearance in its cell) reaches the target
+            // interior clearance in its cell) reaches the target; option o
+            // is level o / 2 with half-width 1 + o % 2
+            const float tgt = (float)(target * cd.inv_cell);
             int opt = nopt - 1;
             for (int o = 0; o < nopt; ++o) {
-              const int l = kOptLevel[o];
-              const double c = ldexp(cd.cell, l);
-              double f = c;
+              const int l = o >> 1;
+              const float w = (float)(1 << l);
+              float f = w;
 #pragma unroll
               for (int a = 0; a < 3; ++a) {
-                const double lo = cd.origin[a] + (double)(c0[a] >> l) * c;
-                f = fmin(f, fmin(r[a] - lo, lo + c - r[a]));
+                const float off = (float)(c0[a] & ((1 << l) - 1)) + u[a];
+                f = fminf(f, fminf(off, w - off));
               }
-              if ((double)kOptHalf[o] * c + fmax(f, 0.0) >= target) { opt = o; break; }
+              if ((float)(1 + (o & 1)) * w + fmaxf(f, 0.f) >= tgt) { opt = o; break; }
             }
-            const int lt = kOptLevel[opt], half = kOptHalf[opt];
+            const int lt = opt >> 1, half = 1 + (opt & 1);
             const int32_t cl[3] = {c0[0] >> lt, c0[1] >> lt, c0[2] >> lt};
             if (cl[0] != cc0[0] || cl[1] != cc0[1] || cl[2] != cc0[2] || cloud != ccloud ||
                 opt != copt) {
