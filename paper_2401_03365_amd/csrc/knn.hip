@@ -51,6 +51,13 @@ struct alignas(16) ChunkQueries {
   int32_t cloud[kChunk];
 };
 
+// List entries of up to 16 consecutive queries (entry j of the g-th query of
+// the group at [g][j]), flushed to the tiles as 64-byte segments per entry.
+constexpr int kListGroup = 16;
+struct alignas(16) ListGroup {
+  int32_t e[kListGroup][64];
+};
+
 struct alignas(16) WaveLds {
   uint32_t cstart[128];
   uint32_t cexcl[128];
@@ -596,10 +603,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
                                                             double *__restrict__ out_keys) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ ChunkQueries chq[kWavesPerBlock];
+  __shared__ ListGroup lgr[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   WaveLds &L = lds[wv];
   ChunkQueries &Q = chq[wv];
+  ListGroup &LG = lgr[wv];
+  // every slot is searched: lists are gathered per group of queries and
+  // written as whole segments (a refresh leaves other slots' rows as they are)
+  const bool grouped = slot_flag == nullptr;
   const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
   const int nopt = 2 * g.n_levels;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -818,7 +830,30 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       // lists are stored per tile of 64 consecutive queries, neighbour-major:
       // entry j of query p at [(p / 64) * 64 k + j * 64 + p % 64]; entries
       // past the cloud's size are -1
-      if (lane < k) nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = valid ? mp : -1;
+      if (lane < k) {
+        const int32_t e = valid ? mp : -1;
+        if (grouped) LG.e[j & (kListGroup - 1)][lane] = e;
+        else nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = e;
+      }
+      if (grouped && ((j & (kListGroup - 1)) == kListGroup - 1 || p == pend - 1)) {
+        // the group's row segments, 16 entries (64 B) per list row; rows of
+        // slots past the last query hold -1
+        wave_sync();
+        const int g0 = j & ~(kListGroup - 1), gn = (j & (kListGroup - 1)) + 1;
+        if (lane < k) {
+          int4 *dst = reinterpret_cast<int4 *>(nbr + (p >> 6) * 64 * k + lane * 64 +
+                                               ((p0 + g0) & 63));
+#pragma unroll
+          for (int q4 = 0; q4 < kListGroup / 4; ++q4) {
+            int32_t v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              v[t] = (4 * q4 + t < gn) ? LG.e[4 * q4 + t][lane] : -1;
+            dst[q4] = make_int4(v[0], v[1], v[2], v[3]);
+          }
+        }
+        wave_sync();
+      }
       // the list is sorted when it keeps extra entries: its k-th key is in
       // lane k - 1
       const uint64_t kth = k > kfit ? readlane_u64(mk, k - 1) : 0ull;
