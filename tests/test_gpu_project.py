@@ -245,6 +245,23 @@ def tile_lists(g, n, k_list, kfit):
     return torch.sort(out, dim=1).values.cpu().numpy()
 
 
+@pytest.mark.parametrize("n,k,extra", [(20203, 32, 0), (1000, 48, 16), (77, 8, 5)])
+def test_tile_lists_of_every_slot(orc, n, k, extra):
+    # the search writes the lists of 16 consecutive queries as whole row
+    # segments; sizes that end inside a segment and inside a tile, with and
+    # without extra entries: the first k of every slot are the oracle's set
+    P = synth.torus(n, sigma=0.005, seed=41)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    g.project(Pt.double(), k, "fp32", search_extra=extra)
+    torch.cuda.synchronize()
+    got = tile_lists(g, n, k + extra, k)
+    ref_nbr, _ = orc.knn(P.astype(np.float64), P.astype(np.float64), k)
+    np.testing.assert_array_equal(got, np.sort(ref_nbr, axis=1))
+
+
 def test_refresh_without_reranking_keeps_exact_sets(orc):
     # passes 1-2 fresh (64 kept), pass 3 refreshed: most lists are settled
     # one lane per slot without re-ranking; every set must equal the oracle's
