@@ -593,6 +593,9 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
 // squared distance, from the anchor; +inf when the list holds the whole
 // cloud; -1 for a non-finite query or a list without extra entries, which a
 // refresh then searches afresh) serve later refreshes.
+// kPlain: k == kfit, every slot searched, no caller lists (the common case,
+// compiled without the branches of the others).
+template <bool kPlain>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
                                                             int32_t kfit, double support_r_h,
                                                             int32_t *__restrict__ nbr,
@@ -611,7 +614,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
   ListGroup &LG = lgr[wv];
   // every slot is searched: lists are gathered per group of queries and
   // written as whole segments (a refresh leaves other slots' rows as they are)
-  const bool grouped = slot_flag == nullptr;
+  const bool grouped = kPlain || slot_flag == nullptr;
+  if (kPlain) {
+    kfit = k;
+    slot_flag = nullptr;
+    out_nbr = nullptr;
+    out_keys = nullptr;
+  }
   const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
   const int nopt = 2 * g.n_levels;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -824,7 +833,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       uint64_t mk = lane < ntop ? s.key[0] : kEmptyKey;
       int32_t mi = lane < ntop ? s.idx[0] : 0x7fffffff;
       int32_t mp = lane < ntop ? s.pos[0] : -1;
-      if (k > kfit || out_nbr || out_keys) sort_lanes(mk, mi, mp, lane);  // valid entries first
+      if (!kPlain && (k > kfit || out_nbr || out_keys))
+        sort_lanes(mk, mi, mp, lane);  // valid entries first
       const bool valid = lane < ntop;
       const uint32_t m = popc(__ballot(valid && lane < kfit && bitsd(mk) <= rad2));
       // lists are stored per tile of 64 consecutive queries, neighbour-major:
@@ -856,13 +866,17 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       }
       // the list is sorted when it keeps extra entries: its k-th key is in
       // lane k - 1
-      const uint64_t kth = k > kfit ? readlane_u64(mk, k - 1) : 0ull;
+      const uint64_t kth = (!kPlain && k > kfit) ? readlane_u64(mk, k - 1) : 0ull;
       if (lane == 0) {
         support[p] = (uint8_t)((finite && ntop >= kfit) ? m : 0);
         double *an = anchor + 4 * p;
-        an[0] = r[0]; an[1] = r[1]; an[2] = r[2];
-        an[3] = (!finite || k == kfit) ? -1.0
-                : (ntop < k ? __longlong_as_double(0x7ff0000000000000ll) : bitsd(kth));
+        if (kPlain) {
+          an[3] = -1.0;  // no extra entries: a refresh searches afresh
+        } else {
+          an[0] = r[0]; an[1] = r[1]; an[2] = r[2];
+          an[3] = (!finite || k == kfit) ? -1.0
+                  : (ntop < k ? __longlong_as_double(0x7ff0000000000000ll) : bitsd(kth));
+        }
       }
       if (lane < kfit) {
         if (out_nbr) out_nbr[qi * kfit + lane] = valid ? mi : -1;
@@ -1130,9 +1144,13 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
     hipLaunchKernelGGL(k_knn_refresh, dim3((unsigned)blocks), dim3(256), 0, s, g, qv, k, kfit,
                        support_r_h, nbr, support, anchor, flag, lane_pass, out_nbr, out_keys);
   }
-  hipLaunchKernelGGL(k_knn, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g, qv, k,
-                     kfit, support_r_h, nbr, support, anchor, refresh ? flag : nullptr, out_nbr,
-                     out_keys);
+  if (k == kfit && !refresh && !out_nbr && !out_keys)
+    hipLaunchKernelGGL(k_knn<true>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
+                       qv, k, kfit, support_r_h, nbr, support, anchor, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL(k_knn<false>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
+                       qv, k, kfit, support_r_h, nbr, support, anchor, refresh ? flag : nullptr,
+                       out_nbr, out_keys);
   return hipGetLastError();
 }
 
