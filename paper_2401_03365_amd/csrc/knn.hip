@@ -593,9 +593,12 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
 // squared distance, from the anchor; +inf when the list holds the whole
 // cloud; -1 for a non-finite query or a list without extra entries, which a
 // refresh then searches afresh) serve later refreshes.
-// kPlain: k == kfit, every slot searched, no caller lists (the common case,
-// compiled without the branches of the others).
-template <bool kPlain>
+// kMode: kPlain (k == kfit, every slot searched, no caller lists: the
+// common case), kExtra (k > kfit, every slot, no caller lists: a search that
+// keeps entries for a refresh) or kAny; each compiled without the branches of
+// the others.
+constexpr int kPlain = 0, kExtra = 1, kAny = 2;
+template <int kMode>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
                                                             int32_t kfit, double support_r_h,
                                                             int32_t *__restrict__ nbr,
@@ -614,9 +617,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
   ListGroup &LG = lgr[wv];
   // every slot is searched: lists are gathered per group of queries and
   // written as whole segments (a refresh leaves other slots' rows as they are)
-  const bool grouped = kPlain || slot_flag == nullptr;
-  if (kPlain) {
-    kfit = k;
+  const bool grouped = kMode != kAny || slot_flag == nullptr;
+  if (kMode != kAny) {
+    if (kMode == kPlain) kfit = k;
     slot_flag = nullptr;
     out_nbr = nullptr;
     out_keys = nullptr;
@@ -833,7 +836,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       uint64_t mk = lane < ntop ? s.key[0] : kEmptyKey;
       int32_t mi = lane < ntop ? s.idx[0] : 0x7fffffff;
       int32_t mp = lane < ntop ? s.pos[0] : -1;
-      if (!kPlain && (k > kfit || out_nbr || out_keys))
+      if (kMode == kExtra || (kMode == kAny && (k > kfit || out_nbr || out_keys)))
         sort_lanes(mk, mi, mp, lane);  // valid entries first
       const bool valid = lane < ntop;
       const uint32_t m = popc(__ballot(valid && lane < kfit && bitsd(mk) <= rad2));
@@ -866,11 +869,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       }
       // the list is sorted when it keeps extra entries: its k-th key is in
       // lane k - 1
-      const uint64_t kth = (!kPlain && k > kfit) ? readlane_u64(mk, k - 1) : 0ull;
+      const uint64_t kth = (kMode != kPlain && k > kfit) ? readlane_u64(mk, k - 1) : 0ull;
       if (lane == 0) {
         support[p] = (uint8_t)((finite && ntop >= kfit) ? m : 0);
         double *an = anchor + 4 * p;
-        if (kPlain) {
+        if (kMode == kPlain) {
           an[3] = -1.0;  // no extra entries: a refresh searches afresh
         } else {
           an[0] = r[0]; an[1] = r[1]; an[2] = r[2];
@@ -1144,11 +1147,15 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
     hipLaunchKernelGGL(k_knn_refresh, dim3((unsigned)blocks), dim3(256), 0, s, g, qv, k, kfit,
                        support_r_h, nbr, support, anchor, flag, lane_pass, out_nbr, out_keys);
   }
-  if (k == kfit && !refresh && !out_nbr && !out_keys)
-    hipLaunchKernelGGL(k_knn<true>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
+  const bool own = !refresh && !out_nbr && !out_keys;
+  if (own && k == kfit)
+    hipLaunchKernelGGL(k_knn<kPlain>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
+                       qv, k, kfit, support_r_h, nbr, support, anchor, nullptr, nullptr, nullptr);
+  else if (own)
+    hipLaunchKernelGGL(k_knn<kExtra>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
                        qv, k, kfit, support_r_h, nbr, support, anchor, nullptr, nullptr, nullptr);
   else
-    hipLaunchKernelGGL(k_knn<false>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
+    hipLaunchKernelGGL(k_knn<kAny>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
                        qv, k, kfit, support_r_h, nbr, support, anchor, refresh ? flag : nullptr,
                        out_nbr, out_keys);
   return hipGetLastError();
