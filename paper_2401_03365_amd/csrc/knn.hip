@@ -595,9 +595,9 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
 // refresh then searches afresh) serve later refreshes.
 // kMode: kPlain (k == kfit, every slot searched, no caller lists: the
 // common case), kExtra (k > kfit, every slot, no caller lists: a search that
-// keeps entries for a refresh) or kAny; each compiled without the branches of
-// the others.
-constexpr int kPlain = 0, kExtra = 1, kAny = 2;
+// keeps entries for a refresh), kFlagged (the slots a refresh left, no
+// caller lists) or kAny; each compiled without the branches of the others.
+constexpr int kPlain = 0, kExtra = 1, kFlagged = 2, kAny = 3;
 template <int kMode>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
                                                             int32_t kfit, double support_r_h,
@@ -617,10 +617,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
   ListGroup &LG = lgr[wv];
   // every slot is searched: lists are gathered per group of queries and
   // written as whole segments (a refresh leaves other slots' rows as they are)
-  const bool grouped = kMode != kAny || slot_flag == nullptr;
+  const bool grouped = kMode == kPlain || kMode == kExtra || (kMode == kAny && !slot_flag);
   if (kMode != kAny) {
     if (kMode == kPlain) kfit = k;
-    slot_flag = nullptr;
+    if (kMode != kFlagged) slot_flag = nullptr;
     out_nbr = nullptr;
     out_keys = nullptr;
   }
@@ -836,7 +836,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       uint64_t mk = lane < ntop ? s.key[0] : kEmptyKey;
       int32_t mi = lane < ntop ? s.idx[0] : 0x7fffffff;
       int32_t mp = lane < ntop ? s.pos[0] : -1;
-      if (kMode == kExtra || (kMode == kAny && (k > kfit || out_nbr || out_keys)))
+      if (((kMode == kExtra || kMode == kFlagged) && k > kfit) ||
+          (kMode == kAny && (k > kfit || out_nbr || out_keys)))
         sort_lanes(mk, mi, mp, lane);  // valid entries first
       const bool valid = lane < ntop;
       const uint32_t m = popc(__ballot(valid && lane < kfit && bitsd(mk) <= rad2));
@@ -1154,6 +1155,9 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
   else if (own)
     hipLaunchKernelGGL(k_knn<kExtra>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
                        qv, k, kfit, support_r_h, nbr, support, anchor, nullptr, nullptr, nullptr);
+  else if (refresh && !out_nbr && !out_keys)
+    hipLaunchKernelGGL(k_knn<kFlagged>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s,
+                       g, qv, k, kfit, support_r_h, nbr, support, anchor, flag, nullptr, nullptr);
   else
     hipLaunchKernelGGL(k_knn<kAny>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
                        qv, k, kfit, support_r_h, nbr, support, anchor, refresh ? flag : nullptr,
