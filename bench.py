@@ -447,7 +447,8 @@ def main():
     else:
         flops = nq * SEARCH_FP64_FLOPS_PER_QUERY
         achieved = flops / (br32["search"] / 1000.0) / 1e12
-        roof = {"kernel": "k_knn", "bound": "alu", "achieved": achieved,
+        roof = {"kernel": "k_knn (passes 1-2: k_knn<0> plain, k_knn<1> with extra entries)",
+                "bound": "alu", "achieved": achieved,
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                 "traffic": search_traffic_bytes(args)}
         if roof["traffic"] is not None:
