@@ -371,8 +371,11 @@ __device__ __forceinline__ void backward_one(const GridView &g, const QueryView 
   store_vec(grad_q, qv.is_f64, qi, rb);
 }
 
+// FP32 moments: 4 waves per SIMD (the LDS table allows 5 blocks per CU; the
+// neighbour loops are latency-bound and gain more from the waves than they
+// lose to the spills of the FP64 solve state); FP64: the 56 KB table allows 2.
 template <bool kF32>
-__global__ __launch_bounds__(kBlock) void k_mls_backward(GridView g, QueryView qv, int32_t k,
+__global__ __launch_bounds__(kBlock, kF32 ? 4 : 2) void k_mls_backward(GridView g, QueryView qv, int32_t k,
                                                          double support_radius_h,
                                                          int32_t min_support,
                                                          const int32_t *__restrict__ nbr,
