@@ -63,7 +63,25 @@ __global__ __launch_bounds__(kThreads) void k_bbox(const float *__restrict__ pts
     }
     bad += (uint32_t)__shfl_xor((int)bad, off);
   }
+  // one set of atomics per block (atomics on the cloud's 7 words serialise)
+  __shared__ uint32_t part[kThreads / 64][7];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      part[w][a] = mn[a];
+      part[w][3 + a] = mx[a];
+    }
+    part[w][6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < kThreads / 64; ++v) {
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = min(mn[a], part[v][a]);
+        mx[a] = max(mx[a], part[v][3 + a]);
+      }
+      bad += part[v][6];
+    }
     for (int a = 0; a < 3; ++a) {
       atomicMin(bbox + 6 * c + a, mn[a]);
       atomicMax(bbox + 6 * c + 3 + a, mx[a]);
@@ -345,9 +363,9 @@ hipError_t launch_bbox(const float *pts, const int64_t *offsets_dev, int32_t n_c
                        hipStream_t s) {
   hipLaunchKernelGGL(k_bbox_init, dim3(blocks_for(6 * n_clouds, 256)), dim3(256), 0, s, bbox_bits,
                      nonfinite, n_clouds);
-  unsigned gx = blocks_for(max_cloud, kThreads * 8);
+  unsigned gx = blocks_for(max_cloud, kThreads * 32);
   if (gx < 1) gx = 1;
-  if (gx > 2048) gx = 2048;
+  if (gx > 512) gx = 512;
   hipLaunchKernelGGL(k_bbox, dim3(gx, n_clouds), dim3(kThreads), 0, s, pts, offsets_dev,
                      bbox_bits, nonfinite);
   return hipGetLastError();
