@@ -11,9 +11,11 @@ NumPy arrays. Every function follows the paper's MLS projection:
 * ``knn``       -- brute-force k nearest neighbours on canonical FP64 keys,
                    ties to the smaller index (neighbourhood search of
                    Section 2 / Section 2.2, here with k neighbours).
-* ``project``   -- reference plane (Section 1.4, Eq. (1.1) at t = 0), local
-                   frame, weighted quadratic height fit and projection
-                   (Section 2.1, Algorithm 1), outlier rule (Section 3.3).
+* ``project``   -- reference plane (Section 1.4, Eq. (1.1) at t = 0, or
+                   ``plane_iters`` steps that move the weights to the plane's
+                   own projection q = r + t n), local frame, weighted
+                   quadratic height fit and projection (Section 2.1,
+                   Algorithm 1), outlier rule (Section 3.3).
 * ``grad_fd``   -- J^T g by central finite differences with lists fixed.
 
 Parity pins for each function are in ``tests/test_oracle_*.py``.
@@ -61,7 +63,7 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_knn.argtypes = [P, i64, P, i64, i32, P, P]
         lib.orc_knn.restype = ctypes.c_int
-        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, P, P, P]
+        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, P, P, P]
         lib.orc_project.restype = ctypes.c_int
         lib.orc_grad_fd.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, P, f64, P, P]
         lib.orc_grad_fd.restype = ctypes.c_int
@@ -94,10 +96,12 @@ def knn(P, Q, k):
     return idx, key
 
 
-def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=False):
+def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=False,
+            plane_iters=0):
     """One MLS projection pass. Returns (out (m,3) float64, status uint8 (m,)
     [, diag (m, 24)]). ``nbr`` are original indices (m, k); computed by brute
-    force when omitted."""
+    force when omitted. ``plane_iters``: steps of the reference plane with the
+    weights at the plane's own projection of the query (0: weights at r)."""
     lib = _load()
     P, Q = _c64(P), _c64(Q)
     m = Q.shape[0]
@@ -110,7 +114,8 @@ def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=Fals
     st = np.empty(m, dtype=np.uint8)
     dg = np.empty((m, lib.orc_diag_stride()), dtype=np.float64) if diag else None
     rc = lib.orc_project(_ptr(P), P.shape[0], _ptr(Q), m, int(k), float(h), _ptr(nbr),
-                         float(support_radius_h), int(min_support), _ptr(out), _ptr(st), _ptr(dg))
+                         float(support_radius_h), int(min_support), int(plane_iters), _ptr(out),
+                         _ptr(st), _ptr(dg))
     if rc:
         raise ValueError("orc_project failed (%d)" % rc)
     return (out, st, dg) if diag else (out, st)

@@ -23,6 +23,15 @@
  *   O5  n = unit eigenvector of the smallest eigenvalue of C (cyclic Jacobi).
  *       This is the minimiser of Eq. (1.1) over |n| = 1 and D for the weights
  *       taken at r (the one-step t = 0 form of the reference plane).
+ *   O5b (plane_iters = T > 0) Section 1.4 ties the weights of Eq. (1.1) to
+ *       the projection q = r + t n of r onto the plane itself. Starting from
+ *       the t = 0 plane, T times: weights w_i = exp(-|d_i - tau n|^2) with
+ *       tau = <n, mu> of the current plane (centred at its q), moments about r
+ *       as in O4, the plane of O5 again. A fixed point of this map is a plane
+ *       that minimises Eq. (1.1) with the weights taken at its own q; from
+ *       t = 0 it approaches the fixed point nearest to r (the paper's local
+ *       minimum with the smallest t). The number of steps is fixed (no
+ *       convergence test), so every implementation takes the same steps.
  *   O6  plane H through r + h*mu with normal n; its origin q is the orthogonal
  *       projection of r onto H: q = r + h <n, mu> n (Section 2.1: the
  *       projection of the point onto H defines the origin q).
@@ -203,7 +212,41 @@ typedef struct {
   int min_support_fit;     /* O9 minimum support for the quadratic (6) */
   double pivot_tol;        /* O9 relative Cholesky pivot tolerance (1e-12) */
   double ambig_gap;        /* O5 relative eigen-gap for the flag (1e-6) */
+  int plane_iters;         /* O5b refinements of the reference plane (0) */
 } orc_consts;
+
+
+/* O4 + O5 with the weights centred at r + h * tau * c (tau = 0: at r):
+ * weighted moments about r in units of h, mu, C and the eigenpairs;
+ * returns S0, writes the unit normal, the eigenvalues and mu. */
+static double plane_fit(const double *P, const double *r, const int32_t *nb, int k, double h,
+                        double tau, const double *c, double nrm[3], double lam[3],
+                        double mu[3]) {
+  double S0 = 0.0, S1[3] = {0, 0, 0}, S2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = 0; j < k; ++j) {
+    const double *p = P + 3 * (int64_t)nb[j];
+    double d[3] = {(p[0] - r[0]) / h, (p[1] - r[1]) / h, (p[2] - r[2]) / h};
+    double e[3] = {d[0] - tau * c[0], d[1] - tau * c[1], d[2] - tau * c[2]};
+    double w = exp(-dot3(e, e));
+    S0 += w;
+    for (int a = 0; a < 3; ++a) {
+      S1[a] += w * d[a];
+      for (int b = 0; b < 3; ++b) S2[a][b] += w * d[a] * d[b];
+    }
+  }
+  for (int a = 0; a < 3; ++a) mu[a] = S1[a] / S0;
+  double C[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C[a][b] = S2[a][b] / S0 - mu[a] * mu[b];
+  double V[3][3];
+  jacobi3(C, V, lam);
+  nrm[0] = V[0][0];
+  nrm[1] = V[1][0];
+  nrm[2] = V[2][0];
+  double nn = sqrt(dot3(nrm, nrm));
+  for (int a = 0; a < 3; ++a) nrm[a] /= nn;
+  return S0;
+}
 
 /* O3-O10 for one query with a fixed neighbour list nb[0..k). */
 static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
@@ -237,29 +280,15 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
     return ORC_PT_OUTLIER;
   }
 
-  /* O4: weighted first and second moments about r in units of h */
-  double S0 = 0.0, S1[3] = {0, 0, 0}, S2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int j = 0; j < k; ++j) {
-    const double *p = P + 3 * (int64_t)nb[j];
-    double d[3] = {(p[0] - r[0]) / h, (p[1] - r[1]) / h, (p[2] - r[2]) / h};
-    double w = exp(-dot3(d, d));
-    S0 += w;
-    for (int a = 0; a < 3; ++a) {
-      S1[a] += w * d[a];
-      for (int b = 0; b < 3; ++b) S2[a][b] += w * d[a] * d[b];
-    }
+  /* O4, O5: the plane for the weights at r */
+  double nrm[3], lam[3], mu[3];
+  const double zero3[3] = {0.0, 0.0, 0.0};
+  double S0 = plane_fit(P, r, nb, k, h, 0.0, zero3, nrm, lam, mu);
+  /* O5b: weights moved to the current plane's projection of r */
+  for (int it = 0; it < cs->plane_iters; ++it) {
+    double c[3] = {nrm[0], nrm[1], nrm[2]};
+    S0 = plane_fit(P, r, nb, k, h, dot3(nrm, mu), c, nrm, lam, mu);
   }
-  double mu[3] = {S1[0] / S0, S1[1] / S0, S1[2] / S0};
-  double C[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) C[a][b] = S2[a][b] / S0 - mu[a] * mu[b];
-
-  /* O5 */
-  double V[3][3], lam[3];
-  jacobi3(C, V, lam);
-  double nrm[3] = {V[0][0], V[1][0], V[2][0]};
-  double nn = sqrt(dot3(nrm, nrm));
-  for (int a = 0; a < 3; ++a) nrm[a] /= nn;
   uint8_t flags = 0;
   if (lam[1] - lam[0] < cs->ambig_gap * lam[2]) flags |= ORC_PT_FLAG_AMBIGUOUS;
 
@@ -355,23 +384,25 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
   return ORC_PT_OK | flags;
 }
 
-static void fill_consts(orc_consts *cs, double support_radius_h, int min_support) {
+static void fill_consts(orc_consts *cs, double support_radius_h, int min_support,
+                        int plane_iters) {
   cs->support_radius_h = support_radius_h;
   cs->min_support = min_support;
   cs->min_support_fit = 6;
   cs->pivot_tol = 1e-12;
   cs->ambig_gap = 1e-6;
+  cs->plane_iters = plane_iters;
 }
 
 /* Exported projection with given neighbour lists (m x k original indices). */
 int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
                 int32_t k, double h, const int32_t *nbr,
-                double support_radius_h, int32_t min_support, double *out,
-                uint8_t *status, double *diag) {
+                double support_radius_h, int32_t min_support, int32_t plane_iters,
+                double *out, uint8_t *status, double *diag) {
   (void)n;
-  if (k <= 0 || !(h > 0.0) || !isfinite(h)) return 1;
+  if (k <= 0 || !(h > 0.0) || !isfinite(h) || plane_iters < 0) return 1;
   orc_consts cs;
-  fill_consts(&cs, support_radius_h, min_support);
+  fill_consts(&cs, support_radius_h, min_support, plane_iters);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t j = 0; j < m; ++j) {
     status[j] = project_one(P, Q + 3 * j, nbr + j * k, k, h, &cs, out + 3 * j,
@@ -391,7 +422,7 @@ int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
                 double *gq, double *gp) {
   if (k <= 0 || !(h > 0.0)) return 1;
   orc_consts cs;
-  fill_consts(&cs, support_radius_h, min_support);
+  fill_consts(&cs, support_radius_h, min_support, 0);
   memset(gp, 0, sizeof(double) * 3 * (size_t)n);
   double step = rel_step * h;
   int nthr_fail = 0;
