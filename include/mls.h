@@ -80,6 +80,7 @@ enum {
 };
 
 #define MLS_MAX_K 64
+#define MLS_MAX_PLANE_ITERS 16
 
 typedef struct mls_grid mls_grid; /* opaque, host-side handle */
 
@@ -94,6 +95,14 @@ typedef struct {
   int32_t search_extra;     /* extra neighbours the search keeps per query
                                beyond k (k + search_extra <= MLS_MAX_K), for
                                MLS_STAGE_REFRESH in later passes; 0 = none */
+  int32_t plane_iters;      /* steps of the reference plane with the weights
+                               of Eq. (1.1) at the plane's own projection
+                               q = r + t n of the query (Section 1.4), from
+                               the plane with the weights at r (t = 0);
+                               0 <= plane_iters <= MLS_MAX_PLANE_ITERS; 0 =
+                               the t = 0 plane. Forward only: the adjoint
+                               returns MLS_ERR_UNSUPPORTED for a nonzero
+                               value. */
 } mls_params;
 
 /* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and

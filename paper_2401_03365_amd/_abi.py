@@ -15,6 +15,7 @@ MLS_OK, MLS_ERR_INVALID_ARGUMENT, MLS_ERR_TOO_FEW_POINTS = 0, 1, 2
 MLS_ERR_UNSUPPORTED, MLS_ERR_WORKSPACE_TOO_SMALL, MLS_ERR_OUT_OF_MEMORY, MLS_ERR_HIP = 3, 4, 5, 6
 MLS_F32, MLS_F64 = 0, 1
 MLS_MAX_K = 64
+MLS_MAX_PLANE_ITERS = 16
 MLS_PREC_FP64, MLS_PREC_FP32_MOMENTS = 0, 1
 MLS_STAGE_ALL, MLS_STAGE_SEARCH, MLS_STAGE_FIT, MLS_STAGE_REFRESH = 0, 1, 2, 4
 PT_OK, PT_OUTLIER, PT_PLANE_ONLY, PT_NONFINITE, PT_FLAG_AMBIGUOUS = 0, 1, 2, 3, 0x10
@@ -29,7 +30,8 @@ _ST = ctypes.c_int
 class MlsParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("support_radius_h", ctypes.c_double), ("min_support", ctypes.c_int32),
-                ("stages", ctypes.c_int32), ("search_extra", ctypes.c_int32)]
+                ("stages", ctypes.c_int32), ("search_extra", ctypes.c_int32),
+                ("plane_iters", ctypes.c_int32)]
 
 
 class MlsGridInfo(ctypes.Structure):

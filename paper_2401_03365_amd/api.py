@@ -146,30 +146,34 @@ class Grid:
         _abi.check(code, "mls_knn")
         return (nbr, keys) if return_keys else nbr
 
-    def _params(self, k, precision, support_radius_h, min_support, stages=0, search_extra=0):
+    def _params(self, k, precision, support_radius_h, min_support, stages=0, search_extra=0,
+                plane_iters=0):
         if precision not in PRECISIONS:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
                               support_radius_h=float(support_radius_h),
                               min_support=int(min_support), stages=int(stages),
-                              search_extra=int(search_extra))
+                              search_extra=int(search_extra), plane_iters=int(plane_iters))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
                 support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
                 status: Optional[torch.Tensor] = None, search_extra: int = 0,
-                refresh: bool = False):
+                refresh: bool = False, plane_iters: int = 0):
         """One MLS projection pass. Returns (out, status[, neighbours]).
         ``stages``: 0 = search and fit, 1 = search only (lists stay in the
         grid's workspace), 2 = fit only from the preceding search.
         ``search_extra``: neighbours kept beyond k for later refreshes;
         ``refresh``: start the search from the lists of the previous search
-        of the same queries' slots (exact; see MLS_STAGE_REFRESH)."""
+        of the same queries' slots (exact; see MLS_STAGE_REFRESH);
+        ``plane_iters``: steps of the reference plane with the weights at
+        the plane's own projection of the query (0: weights at the query)."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
         if refresh:
             stages = (stages or (_abi.MLS_STAGE_SEARCH | _abi.MLS_STAGE_FIT)) | _abi.MLS_STAGE_REFRESH
-        params = self._params(k, precision, support_radius_h, min_support, stages, search_extra)
+        params = self._params(k, precision, support_radius_h, min_support, stages, search_extra,
+                              plane_iters)
         if out is None:
             out = torch.empty_like(queries)
         if status is None:

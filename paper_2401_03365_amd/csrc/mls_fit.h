@@ -232,6 +232,41 @@ __device__ __forceinline__ void pass1_moments(const GridView &g, const int32_t *
   for (int a = 0; a < 6; ++a) S2[a] = A.value(4 + a);
 }
 
+// The moments of pass 1 (about r) with the weights centred at q = r + h tn
+// instead of r: w_i = exp(-|d_i - tn|^2), tn = t n in units of h (a step of
+// the reference plane toward the plane whose weights sit at its own
+// projection of r, Section 1.4).
+template <bool kF32>
+__device__ __forceinline__ void plane_moments_at(const GridView &g, const int32_t *nb, int k,
+                                                 const Rel<kF32> &rel, const Real<kF32> tn[3],
+                                                 double &S0, double S1[3], double S2[6]) {
+  using T = Real<kF32>;
+  Acc<kF32, 10> A;
+  A.zero();
+  for (int j0 = 0; j0 < k; j0 += kBatch) {
+    float4 PB[kBatch];
+    int32_t id[kBatch];
+    load_batch(g, nb, j0, k, PB, id);
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (j0 + b >= k) break;
+      T dx, dy, dz;
+      rel.d(PB[b], dx, dy, dz);
+      const T ex = dx - tn[0], ey = dy - tn[1], ez = dz - tn[2];
+      const T w = wexp(-(ex * ex + ey * ey + ez * ez));
+      const T wx = w * dx, wy = w * dy, wz = w * dz;
+      A.blk[0] += w;
+      A.blk[1] += wx; A.blk[2] += wy; A.blk[3] += wz;
+      A.blk[4] += wx * dx; A.blk[5] += wx * dy; A.blk[6] += wx * dz;
+      A.blk[7] += wy * dy; A.blk[8] += wy * dz; A.blk[9] += wz * dz;
+    }
+    A.fold();
+  }
+  S0 = A.value(0);
+  for (int a = 0; a < 3; ++a) S1[a] = A.value(1 + a);
+  for (int a = 0; a < 6; ++a) S2[a] = A.value(4 + a);
+}
+
 // The plane quantities of pass 2 in the pass's arithmetic.
 template <bool kF32>
 struct FrameT {

@@ -4,7 +4,10 @@
 // search) and Gaussian width h:
 //   pass 1  d_i = (p_i - r)/h, w_i = exp(-|d_i|^2); S0, S1 = sum w d,
 //           S2 = sum w d d^T (10 sums)                       [Section 1.4, Eq. (1.1)]
-//   plane   C = S2/S0 - mu mu^T, n = smallest eigenvector, q = r + h <n,mu> n
+//   plane   C = S2/S0 - mu mu^T, n = smallest eigenvector, q = r + h <n,mu> n;
+//           with plane_iters > 0, that many more planes from the moments with
+//           the weights centred at the current q (Section 1.4: the weights
+//           of Eq. (1.1) belong to the projection of r onto the plane)
 //   frame   u, v orthonormal on the plane                    [Section 1.4]
 //   pass 2  e_i = d_i - <n,mu> n (= (p_i - q)/h), x = <u,e>, y = <v,e>,
 //           f = <n,e>, w'_i = exp(-|e_i|^2); 15 monomial sums + 6 sums of f
@@ -26,9 +29,9 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <bool kF32>
+template <bool kF32, bool kSteps>
 __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv, int32_t k,
-                                                        int32_t min_support,
+                                                        int32_t min_support, int32_t plane_iters,
                                                         const int32_t *__restrict__ nbr,
                                                         const uint8_t *__restrict__ support,
                                                         void *__restrict__ out,
@@ -59,7 +62,15 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
 
   double S0, S1[3], S2[6];
   pass1_moments<kF32>(g, nb, k, rel, S0, S1, S2);
-  const PlaneFit pf = plane_from_moments(S0, S1, S2, r, h);
+  PlaneFit pf = plane_from_moments(S0, S1, S2, r, h);
+  if (kSteps) {
+    for (int it = 0; it < plane_iters; ++it) {
+      const Real<kF32> tn[3] = {(Real<kF32>)(pf.t * pf.n[0]), (Real<kF32>)(pf.t * pf.n[1]),
+                                (Real<kF32>)(pf.t * pf.n[2])};
+      plane_moments_at<kF32>(g, nb, k, rel, tn, S0, S1, S2);
+      pf = plane_from_moments(S0, S1, S2, r, h);
+    }
+  }
   QuadSums qs;
   pass2_sums<kF32>(g, nb, k, rel, FrameT<kF32>(pf), qs);
 
@@ -82,16 +93,24 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
 }  // namespace
 
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
-                              int32_t precision, int32_t min_support, const int32_t *nbr,
-                              const uint8_t *support, void *out, uint8_t *status, hipStream_t s) {
+                              int32_t precision, int32_t min_support, int32_t plane_iters,
+                              const int32_t *nbr, const uint8_t *support, void *out,
+                              uint8_t *status, hipStream_t s) {
   if (qv.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((qv.n + kBlock - 1) / kBlock);
-  if (precision == MLS_PREC_FP32_MOMENTS)
-    hipLaunchKernelGGL(k_mls_forward<true>, dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, nbr, support, out, status);
+  const bool f32 = precision == MLS_PREC_FP32_MOMENTS;
+  if (f32 && plane_iters == 0)
+    hipLaunchKernelGGL((k_mls_forward<true, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
+                       min_support, 0, nbr, support, out, status);
+  else if (f32)
+    hipLaunchKernelGGL((k_mls_forward<true, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
+                       min_support, plane_iters, nbr, support, out, status);
+  else if (plane_iters == 0)
+    hipLaunchKernelGGL((k_mls_forward<false, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
+                       k, min_support, 0, nbr, support, out, status);
   else
-    hipLaunchKernelGGL(k_mls_forward<false>, dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, nbr, support, out, status);
+    hipLaunchKernelGGL((k_mls_forward<false, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
+                       k, min_support, plane_iters, nbr, support, out, status);
   return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@ brute-force kNN over the whole cloud:
 
   torus 1,010,000 (1 % outliers), k = 32, FP32-moment and FP64 paths;
   height field 10,000,000, k = 48, 3 iterated FP32-moment passes (each pass
-      checked against the oracle fed the GPU's own pass input);
+      checked against the oracle fed the GPU's own pass input), and one
+      pass with 3 steps of the self-consistent reference plane;
   bumped sphere 2,000,000, k = 32, FP32 forward and the adjoint (1,000
       queries against central finite differences);
   batch of 256 clouds, ~30M points, k = 32, FP32.
@@ -110,6 +111,30 @@ def test_heightfield_10m_three_passes(orc):
         check_sample(orc, P64, qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
                      ref_nbr, "fp32")
         cur = out
+
+
+def test_heightfield_10m_plane_steps(orc):
+    # the self-consistent reference plane (3 steps), FP32-moment path, one
+    # call over the whole cloud as timed
+    P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h, cell_size=1.25 * h)
+    rng = np.random.default_rng(25)
+    idx = np.sort(rng.choice(P.shape[0], 192, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    out, st = g.project(Pt.double(), 48, "fp32", plane_iters=3)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    Qs = P64[idx]
+    ref_nbr, _ = orc.knn(P64, Qs, 48)
+    ref, ref_st = orc.project(P64, Qs, 48, h, nbr=ref_nbr, plane_iters=3)
+    st_s = st[idx_t].cpu().numpy()
+    np.testing.assert_array_equal(st_s & 0x0F, ref_st & 0x0F)
+    ok = (ref_st & 0x10) == 0
+    err = np.linalg.norm(out[idx_t].cpu().numpy() - ref, axis=1)[ok] / h
+    assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
 
 
 def test_bumped_sphere_2m_forward_and_adjoint(orc):
