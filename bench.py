@@ -47,6 +47,9 @@ SEARCH_EXTRA = 16
 REFRESH_FROM = 2  # 0-based pass index of the first refreshed pass
 FIT_FLOPS_PER_NEIGHBOUR = 108 + 2
 FIT_FP64_FLOPS_PER_QUERY = 1000
+# one step of the reference plane: the pass-1 moments again with the weights
+# centred at q (34 flop per neighbour plus the shift of 3 subtractions)
+PLANE_STEP_FLOPS = 34 + 3
 # Algorithmic work of the exact search per query: 200 candidate FP64 keys of
 # 10 flop (a 3^3 block of cells whose edge is about the k-th neighbour
 # distance holds 100-300 points on these surfaces).
@@ -102,6 +105,9 @@ def parse():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--c4-n", type=int, default=2_000_000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--plane-iters", type=int, default=3,
+                    help="steps of the self-consistent reference plane in the extra "
+                         "'plane_steps' measurement (0 skips it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MB (3 times) and "
                          "print its bandwidth: the reference for the HBM traffic counters")
@@ -142,8 +148,11 @@ class Timer:
         self.acc = {}
 
 
-def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer):
-    """Returns (ms_per_step, last outputs of pass 1, last final outputs)."""
+def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer,
+              plane_iters=0):
+    """Returns (ms_per_step, last outputs of pass 1, last final outputs).
+    ``plane_iters``: steps of the self-consistent reference plane in every
+    fit."""
     q0 = pts.double()
     first = None
     out = None
@@ -167,7 +176,7 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
                              search_extra=extra, refresh=refresh)
             with ctx("fit"):
                 grid.project(cur, k, precision, stages=2, out=nxt, status=status,
-                             search_extra=extra)
+                             search_extra=extra, plane_iters=plane_iters)
             if p == 0:
                 first = nxt
             cur = nxt
@@ -467,6 +476,28 @@ def main():
            "fp64_path": fp64,
            "roofline": roof}
 
+    first_ps = None
+    if args.plane_iters > 0:
+        # the same step with the reference plane's weights moved to its own
+        # projection of the query (Section 1.4), plane_iters steps per fit
+        timer_ps = Timer(torch)
+        ms_ps, first_ps, _ = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", cell,
+                                       max(1, args.steps // 2), 1, timer_ps,
+                                       plane_iters=args.plane_iters)
+        br_ps = {n: timer_ps.ms(n) for n in ("build", "search", "refresh", "fit")}
+        log("plane steps %d: %.2f ms/step  fit %.2f ms" % (args.plane_iters, ms_ps, br_ps["fit"]))
+        # fit with steps: pass 1 once plus once per step, pass 2 once
+        flops = args.n * (args.k * (FIT_FLOPS_PER_NEIGHBOUR + args.plane_iters * PLANE_STEP_FLOPS)
+                          + (1 + args.plane_iters) * FIT_FP64_FLOPS_PER_QUERY // 2
+                          + FIT_FP64_FLOPS_PER_QUERY // 2)
+        ach = flops / (br_ps["fit"] / 1000.0) / 1e12
+        res["plane_steps"] = {
+            "plane_iters": args.plane_iters, "value": args.n * args.passes / (ms_ps / 1000.0),
+            "unit": "pts/s", "ms_per_step": ms_ps, "breakdown_ms": br_ps,
+            "fit_roofline": {"kernel": "k_mls_forward<fp32, steps>", "bound": "alu",
+                             "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}}
+
     if not args.no_fwd_bwd:
         fb = {}
         fb["heightfield_10M_k48"] = fwd_bwd(api, torch, P, h, args.k,
@@ -511,6 +542,14 @@ def main():
                          "n": int(ok.sum())}
         res["accuracy_pass1_vs_oracle"] = acc
         log("cpu oracle %.0f pts/s on %d cores; accuracy %s" % (len(sample) / dt, cores, acc))
+        if first_ps is not None:
+            ref_ps, ref_ps_st = oracle.project(P64, Q, args.k, h, nbr=nbr,
+                                               plane_iters=args.plane_iters)
+            ok_ps = (ref_ps_st & 0x10) == 0
+            e = np.linalg.norm(first_ps.cpu().numpy()[sample] - ref_ps, axis=1)[ok_ps] / h
+            res["plane_steps"]["accuracy_pass1_vs_oracle"] = {
+                "rms_over_h": float(np.sqrt((e ** 2).mean())), "max_over_h": float(e.max()),
+                "n": int(ok_ps.sum())}
 
     print(json.dumps(res), flush=True)
 
