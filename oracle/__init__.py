@@ -138,7 +138,7 @@ def grad_fd(P, Q, k, h, nbr, gout, rel_step=1e-6, support_radius_h=3.0, min_supp
     return gq, gp
 
 
-def project_passes(P, Q, k, h, passes, support_radius_h=3.0, min_support=3):
+def project_passes(P, Q, k, h, passes, support_radius_h=3.0, min_support=3, plane_iters=0):
     """Iterated passes (queries move, cloud fixed): pass t+1 projects the
     outputs of pass t; a query that was an OUTLIER stays where it is."""
     cur = _c64(Q).copy()
@@ -146,7 +146,7 @@ def project_passes(P, Q, k, h, passes, support_radius_h=3.0, min_support=3):
     st = None
     for _ in range(passes):
         out, st_new = project(P, cur, k, h, support_radius_h=support_radius_h,
-                              min_support=min_support)
+                              min_support=min_support, plane_iters=plane_iters)
         out[frozen] = cur[frozen]
         st_new = np.where(frozen, np.uint8(PT_OUTLIER), st_new)
         frozen |= (st_new & 0x0F) == PT_OUTLIER

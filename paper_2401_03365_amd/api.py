@@ -265,14 +265,15 @@ def build_grid(points, h, cloud_offsets=None, cell_size=None) -> Grid:
 
 
 def project(points: torch.Tensor, h, k: int, precision: str = "fp32", passes: int = 1,
-            cell_size=None, cloud_offsets=None):
+            cell_size=None, cloud_offsets=None, plane_iters: int = 0):
     """Project a cloud onto its own MLS surface ``passes`` times (queries move,
-    the cloud and its grid stay fixed). Returns (out, status)."""
+    the cloud and its grid stay fixed). ``plane_iters``: steps of the
+    self-consistent reference plane per pass. Returns (out, status)."""
     grid = Grid(points, h, cloud_offsets=cloud_offsets, cell_size=cell_size)
     cur = points
     st = None
     for it in range(passes):
-        out, st_new = grid.project(cur, k, precision)
+        out, st_new = grid.project(cur, k, precision, plane_iters=plane_iters)
         if st is not None:
             frozen = (st & 0x0F) == _abi.PT_OUTLIER
             out[frozen] = cur[frozen]

@@ -88,6 +88,36 @@ def test_iterated_passes_with_steps(orc):
         cur = out
 
 
+@pytest.mark.parametrize("iters", [0, 2])
+def test_passes_wrapper_matches_oracle_passes(orc, iters):
+    # the convenience call: grid built once, 2 passes over FP32 queries (the
+    # cloud's dtype), outliers frozen; the oracle takes the same passes on the
+    # FP32-rounded outputs of the previous one
+    P = synth.torus(8000, sigma=0.005, n_outliers=80, seed=49)
+    h = synth.mean_nn_h(P)
+    a = api()
+    out, st = a.project(torch.from_numpy(P).cuda(), h, 24, "fp64", passes=2,
+                        plane_iters=iters)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    cur, ref_st = P64.copy(), None
+    for _ in range(2):
+        ref, st_new = orc.project(P64, cur, 24, h, plane_iters=iters)
+        if ref_st is not None:
+            frozen = (ref_st & 0x0F) == orc.PT_OUTLIER
+            ref[frozen] = cur[frozen]
+            st_new = np.where(frozen, ref_st, st_new)
+        ref_st = st_new
+        cur = ref.astype(np.float32).astype(np.float64)
+    st = st.cpu().numpy()
+    np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    out = out.cpu().numpy().astype(np.float64)
+    diff = np.maximum(np.abs(out - ref) - np.spacing(np.abs(ref).astype(np.float32)), 0)
+    err = np.linalg.norm(diff, axis=1)[ok] / h
+    assert err.max() <= FP64_MAX_H, err.max()
+
+
 def test_steps_move_the_plane(orc):
     # off-surface queries: the stepped plane differs from the t = 0 plane by
     # far more than the tolerance, so the parity above is not vacuous
