@@ -34,6 +34,7 @@ _LIB = os.path.join(_HERE, "libmls_oracle.so")
 
 PT_OK, PT_OUTLIER, PT_PLANE_ONLY, PT_NONFINITE = 0, 1, 2, 3
 PT_FLAG_AMBIGUOUS = 0x10
+PT_FLAG_TRUNCATED = 0x20
 DIAG_FIELDS = {
     "n": slice(0, 3), "lam": slice(3, 6), "q": slice(6, 9), "u": slice(9, 12),
     "v": slice(12, 15), "a": slice(15, 21), "support": 21, "S0": 22,
@@ -63,7 +64,7 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_knn.argtypes = [P, i64, P, i64, i32, P, P]
         lib.orc_knn.restype = ctypes.c_int
-        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, P, P, P]
+        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, i32, P, P, P]
         lib.orc_project.restype = ctypes.c_int
         lib.orc_grad_fd.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, P, f64, P, P]
         lib.orc_grad_fd.restype = ctypes.c_int
@@ -97,11 +98,13 @@ def knn(P, Q, k):
 
 
 def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=False,
-            plane_iters=0):
+            plane_iters=0, ball=False):
     """One MLS projection pass. Returns (out (m,3) float64, status uint8 (m,)
     [, diag (m, 24)]). ``nbr`` are original indices (m, k); computed by brute
     force when omitted. ``plane_iters``: steps of the reference plane with the
-    weights at the plane's own projection of the query (0: weights at r)."""
+    weights at the plane's own projection of the query (0: weights at r).
+    ``ball``: the neighbourhood is the list entries within support_radius_h
+    * h (the paper's radius R); TRUNCATED flags a list wholly inside it."""
     lib = _load()
     P, Q = _c64(P), _c64(Q)
     m = Q.shape[0]
@@ -114,8 +117,8 @@ def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=Fals
     st = np.empty(m, dtype=np.uint8)
     dg = np.empty((m, lib.orc_diag_stride()), dtype=np.float64) if diag else None
     rc = lib.orc_project(_ptr(P), P.shape[0], _ptr(Q), m, int(k), float(h), _ptr(nbr),
-                         float(support_radius_h), int(min_support), int(plane_iters), _ptr(out),
-                         _ptr(st), _ptr(dg))
+                         float(support_radius_h), int(min_support), int(plane_iters),
+                         int(bool(ball)), _ptr(out), _ptr(st), _ptr(dg))
     if rc:
         raise ValueError("orc_project failed (%d)" % rc)
     return (out, st, dg) if diag else (out, st)

@@ -32,6 +32,12 @@
  *       t = 0 it approaches the fixed point nearest to r (the paper's local
  *       minimum with the smallest t). The number of steps is fixed (no
  *       convergence test), so every implementation takes the same steps.
+ *   O3b (ball = 1) the paper's neighbourhood of radius R (Section 1.4, the
+ *       points within R of r) with R = support_radius_h * h: O4, O5b and O8
+ *       use only the list entries whose O1 key is at most R^2. The list holds
+ *       the k nearest, so the ball is complete when fewer than k entries lie
+ *       within R; when all k do, the ball may hold more points than the list
+ *       and the query is flagged TRUNCATED (its k nearest are used).
  *   O6  plane H through r + h*mu with normal n; its origin q is the orthogonal
  *       projection of r onto H: q = r + h <n, mu> n (Section 2.1: the
  *       projection of the point onto H defines the origin q).
@@ -64,6 +70,7 @@
 #define ORC_PT_PLANE_ONLY 2
 #define ORC_PT_NONFINITE 3
 #define ORC_PT_FLAG_AMBIGUOUS 0x10
+#define ORC_PT_FLAG_TRUNCATED 0x20
 
 /* Diagnostics written per query when the caller asks for them. */
 #define ORC_DIAG 24
@@ -213,6 +220,7 @@ typedef struct {
   double pivot_tol;        /* O9 relative Cholesky pivot tolerance (1e-12) */
   double ambig_gap;        /* O5 relative eigen-gap for the flag (1e-6) */
   int plane_iters;         /* O5b refinements of the reference plane (0) */
+  int ball;                /* O3b neighbourhood of radius support_radius_h * h */
 } orc_consts;
 
 
@@ -220,11 +228,12 @@ typedef struct {
  * weighted moments about r in units of h, mu, C and the eigenpairs;
  * returns S0, writes the unit normal, the eigenvalues and mu. */
 static double plane_fit(const double *P, const double *r, const int32_t *nb, int k, double h,
-                        double tau, const double *c, double nrm[3], double lam[3],
-                        double mu[3]) {
+                        double tau, const double *c, double rad2, int ball, double nrm[3],
+                        double lam[3], double mu[3]) {
   double S0 = 0.0, S1[3] = {0, 0, 0}, S2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int j = 0; j < k; ++j) {
     const double *p = P + 3 * (int64_t)nb[j];
+    if (ball && key3(p, r) > rad2) continue; /* O3b */
     double d[3] = {(p[0] - r[0]) / h, (p[1] - r[1]) / h, (p[2] - r[2]) / h};
     double e[3] = {d[0] - tau * c[0], d[1] - tau * c[1], d[2] - tau * c[2]};
     double w = exp(-dot3(e, e));
@@ -283,13 +292,14 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
   /* O4, O5: the plane for the weights at r */
   double nrm[3], lam[3], mu[3];
   const double zero3[3] = {0.0, 0.0, 0.0};
-  double S0 = plane_fit(P, r, nb, k, h, 0.0, zero3, nrm, lam, mu);
+  double S0 = plane_fit(P, r, nb, k, h, 0.0, zero3, rad2, cs->ball, nrm, lam, mu);
   /* O5b: weights moved to the current plane's projection of r */
   for (int it = 0; it < cs->plane_iters; ++it) {
     double c[3] = {nrm[0], nrm[1], nrm[2]};
-    S0 = plane_fit(P, r, nb, k, h, dot3(nrm, mu), c, nrm, lam, mu);
+    S0 = plane_fit(P, r, nb, k, h, dot3(nrm, mu), c, rad2, cs->ball, nrm, lam, mu);
   }
   uint8_t flags = 0;
+  if (cs->ball && msup == k) flags |= ORC_PT_FLAG_TRUNCATED;
   if (lam[1] - lam[0] < cs->ambig_gap * lam[2]) flags |= ORC_PT_FLAG_AMBIGUOUS;
 
   /* O6 */
@@ -325,6 +335,7 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
   memset(b, 0, sizeof b);
   for (int j = 0; j < k; ++j) {
     const double *p = P + 3 * (int64_t)nb[j];
+    if (cs->ball && key3(p, r) > rad2) continue; /* O3b */
     double e[3] = {(p[0] - q[0]) / h, (p[1] - q[1]) / h, (p[2] - q[2]) / h};
     double x = dot3(u, e), y = dot3(v, e), f = dot3(nrm, e);
     double w = exp(-dot3(e, e));
@@ -385,24 +396,25 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
 }
 
 static void fill_consts(orc_consts *cs, double support_radius_h, int min_support,
-                        int plane_iters) {
+                        int plane_iters, int ball) {
   cs->support_radius_h = support_radius_h;
   cs->min_support = min_support;
   cs->min_support_fit = 6;
   cs->pivot_tol = 1e-12;
   cs->ambig_gap = 1e-6;
   cs->plane_iters = plane_iters;
+  cs->ball = ball;
 }
 
 /* Exported projection with given neighbour lists (m x k original indices). */
 int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
                 int32_t k, double h, const int32_t *nbr,
                 double support_radius_h, int32_t min_support, int32_t plane_iters,
-                double *out, uint8_t *status, double *diag) {
+                int32_t ball, double *out, uint8_t *status, double *diag) {
   (void)n;
   if (k <= 0 || !(h > 0.0) || !isfinite(h) || plane_iters < 0) return 1;
   orc_consts cs;
-  fill_consts(&cs, support_radius_h, min_support, plane_iters);
+  fill_consts(&cs, support_radius_h, min_support, plane_iters, ball != 0);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t j = 0; j < m; ++j) {
     status[j] = project_one(P, Q + 3 * j, nbr + j * k, k, h, &cs, out + 3 * j,
@@ -422,7 +434,7 @@ int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
                 double *gq, double *gp) {
   if (k <= 0 || !(h > 0.0)) return 1;
   orc_consts cs;
-  fill_consts(&cs, support_radius_h, min_support, 0);
+  fill_consts(&cs, support_radius_h, min_support, 0, 0);
   memset(gp, 0, sizeof(double) * 3 * (size_t)n);
   double step = rel_step * h;
   int nthr_fail = 0;
