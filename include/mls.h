@@ -68,7 +68,7 @@ typedef enum {
                                eigen-solve and Cholesky in FP64 */
 } mls_precision;
 
-/* Per-point status byte: low nibble is the status, bit 4 a flag. */
+/* Per-point status byte: low nibble is the status, bits 4 and 5 flags. */
 enum {
   MLS_PT_OK = 0,         /* projected onto the local quadratic */
   MLS_PT_OUTLIER = 1,    /* fewer than min_support neighbours within
@@ -76,7 +76,11 @@ enum {
   MLS_PT_PLANE_ONLY = 2, /* quadratic fit singular (support < 6 or a
                             Cholesky pivot <= 1e-12 * max diagonal); out = q */
   MLS_PT_NONFINITE = 3,  /* query has a NaN/Inf coordinate; out = NaN */
-  MLS_PT_FLAG_NORMAL_AMBIGUOUS = 0x10 /* lambda2 - lambda1 < 1e-6 lambda3 */
+  MLS_PT_FLAG_NORMAL_AMBIGUOUS = 0x10, /* lambda2 - lambda1 < 1e-6 lambda3 */
+  MLS_PT_FLAG_TRUNCATED = 0x20         /* ball neighbourhood: every one of the
+                                          k list entries lies within the
+                                          radius, so the ball may hold more
+                                          points than were used */
 };
 
 #define MLS_MAX_K 64
@@ -103,6 +107,14 @@ typedef struct {
                                the t = 0 plane. Forward only: the adjoint
                                returns MLS_ERR_UNSUPPORTED for a nonzero
                                value. */
+  int32_t ball;             /* 0: the neighbourhood is the k nearest; 1: the
+                               paper's neighbourhood of radius R (Section 1.4)
+                               with R = support_radius_h * h, taken as the
+                               k-nearest list entries within R (canonical
+                               keys): exact when fewer than k entries lie
+                               within R, else the status carries
+                               MLS_PT_FLAG_TRUNCATED. Forward only, like
+                               plane_iters. */
 } mls_params;
 
 /* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and

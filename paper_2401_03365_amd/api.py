@@ -147,19 +147,20 @@ class Grid:
         return (nbr, keys) if return_keys else nbr
 
     def _params(self, k, precision, support_radius_h, min_support, stages=0, search_extra=0,
-                plane_iters=0):
+                plane_iters=0, ball=False):
         if precision not in PRECISIONS:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
                               support_radius_h=float(support_radius_h),
                               min_support=int(min_support), stages=int(stages),
-                              search_extra=int(search_extra), plane_iters=int(plane_iters))
+                              search_extra=int(search_extra), plane_iters=int(plane_iters),
+                              ball=int(bool(ball)))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
                 support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
                 status: Optional[torch.Tensor] = None, search_extra: int = 0,
-                refresh: bool = False, plane_iters: int = 0):
+                refresh: bool = False, plane_iters: int = 0, ball: bool = False):
         """One MLS projection pass. Returns (out, status[, neighbours]).
         ``stages``: 0 = search and fit, 1 = search only (lists stay in the
         grid's workspace), 2 = fit only from the preceding search.
@@ -167,13 +168,16 @@ class Grid:
         ``refresh``: start the search from the lists of the previous search
         of the same queries' slots (exact; see MLS_STAGE_REFRESH);
         ``plane_iters``: steps of the reference plane with the weights at
-        the plane's own projection of the query (0: weights at the query)."""
+        the plane's own projection of the query (0: weights at the query);
+        ``ball``: the neighbourhood is the list entries within
+        support_radius_h * h (the paper's radius R), status flag 0x20 where
+        the whole list lies inside it."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
         if refresh:
             stages = (stages or (_abi.MLS_STAGE_SEARCH | _abi.MLS_STAGE_FIT)) | _abi.MLS_STAGE_REFRESH
         params = self._params(k, precision, support_radius_h, min_support, stages, search_extra,
-                              plane_iters)
+                              plane_iters, ball)
         if out is None:
             out = torch.empty_like(queries)
         if status is None:
@@ -265,7 +269,8 @@ def build_grid(points, h, cloud_offsets=None, cell_size=None) -> Grid:
 
 
 def project(points: torch.Tensor, h, k: int, precision: str = "fp32", passes: int = 1,
-            cell_size=None, cloud_offsets=None, plane_iters: int = 0):
+            cell_size=None, cloud_offsets=None, plane_iters: int = 0, ball: bool = False,
+            support_radius_h: float = 3.0):
     """Project a cloud onto its own MLS surface ``passes`` times (queries move,
     the cloud and its grid stay fixed). ``plane_iters``: steps of the
     self-consistent reference plane per pass. Returns (out, status)."""
@@ -273,7 +278,8 @@ def project(points: torch.Tensor, h, k: int, precision: str = "fp32", passes: in
     cur = points
     st = None
     for it in range(passes):
-        out, st_new = grid.project(cur, k, precision, plane_iters=plane_iters)
+        out, st_new = grid.project(cur, k, precision, plane_iters=plane_iters, ball=ball,
+                                   support_radius_h=support_radius_h)
         if st is not None:
             frozen = (st & 0x0F) == _abi.PT_OUTLIER
             out[frozen] = cur[frozen]

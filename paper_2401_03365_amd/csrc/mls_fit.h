@@ -194,12 +194,13 @@ __device__ __forceinline__ void load_batch(const GridView &g, const int32_t *nb,
 // Pass 1: S0 = sum w, S1 = sum w d, S2 = sum w d d^T (packed 00 01 02 11 12 22).
 // With kSupport it also counts the list entries whose canonical FP64 key to r
 // is at most rad2 (into *m) and clears *valid if an entry is not a position.
-template <bool kF32, bool kSupport = false>
+// With kMask, list entry j takes part only if bit j of mask is set.
+template <bool kF32, bool kSupport = false, bool kMask = false>
 __device__ __forceinline__ void pass1_moments(const GridView &g, const int32_t *nb, int k,
                                               const Rel<kF32> &rel, double &S0, double S1[3],
                                               double S2[6], const double *r = nullptr,
                                               double rad2 = 0.0, int *m = nullptr,
-                                              bool *valid = nullptr) {
+                                              bool *valid = nullptr, uint64_t mask = ~0ull) {
   using T = Real<kF32>;
   Acc<kF32, 10> A;
   A.zero();
@@ -218,7 +219,8 @@ __device__ __forceinline__ void pass1_moments(const GridView &g, const int32_t *
       }
       T dx, dy, dz;
       rel.d(PB[b], dx, dy, dz);
-      const T w = wexp(-(dx * dx + dy * dy + dz * dz));
+      T w = wexp(-(dx * dx + dy * dy + dz * dz));
+      if constexpr (kMask) w = ((mask >> (j0 + b)) & 1ull) ? w : (T)0;
       const T wx = w * dx, wy = w * dy, wz = w * dz;
       A.blk[0] += w;
       A.blk[1] += wx; A.blk[2] += wy; A.blk[3] += wz;
@@ -236,10 +238,11 @@ __device__ __forceinline__ void pass1_moments(const GridView &g, const int32_t *
 // instead of r: w_i = exp(-|d_i - tn|^2), tn = t n in units of h (a step of
 // the reference plane toward the plane whose weights sit at its own
 // projection of r, Section 1.4).
-template <bool kF32>
+template <bool kF32, bool kMask = false>
 __device__ __forceinline__ void plane_moments_at(const GridView &g, const int32_t *nb, int k,
                                                  const Rel<kF32> &rel, const Real<kF32> tn[3],
-                                                 double &S0, double S1[3], double S2[6]) {
+                                                 double &S0, double S1[3], double S2[6],
+                                                 uint64_t mask = ~0ull) {
   using T = Real<kF32>;
   Acc<kF32, 10> A;
   A.zero();
@@ -253,7 +256,8 @@ __device__ __forceinline__ void plane_moments_at(const GridView &g, const int32_
       T dx, dy, dz;
       rel.d(PB[b], dx, dy, dz);
       const T ex = dx - tn[0], ey = dy - tn[1], ez = dz - tn[2];
-      const T w = wexp(-(ex * ex + ey * ey + ez * ez));
+      T w = wexp(-(ex * ex + ey * ey + ez * ez));
+      if constexpr (kMask) w = ((mask >> (j0 + b)) & 1ull) ? w : (T)0;
       const T wx = w * dx, wy = w * dy, wz = w * dz;
       A.blk[0] += w;
       A.blk[1] += wx; A.blk[2] += wy; A.blk[3] += wz;
@@ -282,10 +286,10 @@ struct FrameT {
 };
 
 // Pass 2: the 15 monomial sums of M and the 6 sums of b, weights at q.
-template <bool kF32>
+template <bool kF32, bool kMask = false>
 __device__ __forceinline__ void pass2_sums(const GridView &g, const int32_t *nb, int k,
                                            const Rel<kF32> &rel, const FrameT<kF32> &fr,
-                                           QuadSums &qs) {
+                                           QuadSums &qs, uint64_t mask = ~0ull) {
   using T = Real<kF32>;
   Acc<kF32, 21> A;
   A.zero();
@@ -301,7 +305,8 @@ __device__ __forceinline__ void pass2_sums(const GridView &g, const int32_t *nb,
       const T x = fr.u[0] * e0 + fr.u[1] * e1 + fr.u[2] * e2;
       const T y = fr.v[0] * e0 + fr.v[1] * e1 + fr.v[2] * e2;
       const T f = fr.n[0] * e0 + fr.n[1] * e1 + fr.n[2] * e2;
-      const T w = wexp(-(e0 * e0 + e1 * e1 + e2 * e2));
+      T w = wexp(-(e0 * e0 + e1 * e1 + e2 * e2));
+      if constexpr (kMask) w = ((mask >> (j0 + b)) & 1ull) ? w : (T)0;
       const T xx = x * x, xy = x * y, yy = y * y;
       const T wx = w * x, wy = w * y, wxx = w * xx, wxy = w * xy, wyy = w * yy;
       A.blk[0] += w; A.blk[1] += wx; A.blk[2] += wy;

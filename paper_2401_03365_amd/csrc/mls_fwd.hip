@@ -8,6 +8,9 @@
 //           with plane_iters > 0, that many more planes from the moments with
 //           the weights centred at the current q (Section 1.4: the weights
 //           of Eq. (1.1) belong to the projection of r onto the plane)
+// With ball = 1 every sum runs over the list entries whose canonical key to r
+// is at most (support_radius_h h)^2 (the paper's radius-R neighbourhood); a
+// list wholly inside that radius is flagged TRUNCATED.
 //   frame   u, v orthonormal on the plane                    [Section 1.4]
 //   pass 2  e_i = d_i - <n,mu> n (= (p_i - q)/h), x = <u,e>, y = <v,e>,
 //           f = <n,e>, w'_i = exp(-|e_i|^2); 15 monomial sums + 6 sums of f
@@ -29,9 +32,12 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <bool kF32, bool kSteps>
+// kExt: the variant with plane steps and the ball neighbourhood (runtime
+// plane_iters and ball); the plain variant has neither.
+template <bool kF32, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv, int32_t k,
                                                         int32_t min_support, int32_t plane_iters,
+                                                        int32_t ball, double support_radius_h,
                                                         const int32_t *__restrict__ nbr,
                                                         const uint8_t *__restrict__ support,
                                                         void *__restrict__ out,
@@ -61,18 +67,39 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
   const Rel<kF32> rel(r, 1.0 / h);
 
   double S0, S1[3], S2[6];
-  pass1_moments<kF32>(g, nb, k, rel, S0, S1, S2);
-  PlaneFit pf = plane_from_moments(S0, S1, S2, r, h);
-  if (kSteps) {
+  PlaneFit pf;
+  QuadSums qs;
+  uint8_t extra_flags = 0;
+  if (kExt) {
+    // the ball: list entries within the support radius (canonical keys, as
+    // the search counted them)
+    uint64_t mask = ~0ull;
+    if (ball) {
+      const double rad = support_radius_h * h;
+      const double rad2 = rad * rad;
+      mask = 0ull;
+      for (int j = 0; j < k; ++j) {
+        const float4 P = g.pts[clamp_pos(nb[j * 64], g.n_points)];
+        const double key = canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]);
+        mask |= (key <= rad2 ? 1ull : 0ull) << j;
+      }
+      if (m >= k) extra_flags = MLS_PT_FLAG_TRUNCATED;
+    }
+    pass1_moments<kF32, false, true>(g, nb, k, rel, S0, S1, S2, nullptr, 0.0, nullptr, nullptr,
+                                     mask);
+    pf = plane_from_moments(S0, S1, S2, r, h);
     for (int it = 0; it < plane_iters; ++it) {
       const Real<kF32> tn[3] = {(Real<kF32>)(pf.t * pf.n[0]), (Real<kF32>)(pf.t * pf.n[1]),
                                 (Real<kF32>)(pf.t * pf.n[2])};
-      plane_moments_at<kF32>(g, nb, k, rel, tn, S0, S1, S2);
+      plane_moments_at<kF32, true>(g, nb, k, rel, tn, S0, S1, S2, mask);
       pf = plane_from_moments(S0, S1, S2, r, h);
     }
+    pass2_sums<kF32, true>(g, nb, k, rel, FrameT<kF32>(pf), qs, mask);
+  } else {
+    pass1_moments<kF32>(g, nb, k, rel, S0, S1, S2);
+    pf = plane_from_moments(S0, S1, S2, r, h);
+    pass2_sums<kF32>(g, nb, k, rel, FrameT<kF32>(pf), qs);
   }
-  QuadSums qs;
-  pass2_sums<kF32>(g, nb, k, rel, FrameT<kF32>(pf), qs);
 
   double a[6];
   const bool full = (m >= 6) && quad_solve(qs, 1e-12, a);
@@ -87,30 +114,33 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     st = MLS_PT_PLANE_ONLY;
   }
   store_vec(out, qv.is_f64, qi, o);
-  status[qi] = st | pf.flags;
+  status[qi] = st | pf.flags | extra_flags;
 }
 
 }  // namespace
 
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               int32_t precision, int32_t min_support, int32_t plane_iters,
-                              const int32_t *nbr, const uint8_t *support, void *out,
-                              uint8_t *status, hipStream_t s) {
+                              int32_t ball, double support_radius_h, const int32_t *nbr,
+                              const uint8_t *support, void *out, uint8_t *status, hipStream_t s) {
   if (qv.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((qv.n + kBlock - 1) / kBlock);
   const bool f32 = precision == MLS_PREC_FP32_MOMENTS;
-  if (f32 && plane_iters == 0)
+  const bool ext = plane_iters != 0 || ball != 0;
+  if (f32 && !ext)
     hipLaunchKernelGGL((k_mls_forward<true, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, 0, nbr, support, out, status);
+                       min_support, 0, 0, support_radius_h, nbr, support, out, status);
   else if (f32)
     hipLaunchKernelGGL((k_mls_forward<true, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, plane_iters, nbr, support, out, status);
-  else if (plane_iters == 0)
+                       min_support, plane_iters, ball, support_radius_h, nbr, support, out,
+                       status);
+  else if (!ext)
     hipLaunchKernelGGL((k_mls_forward<false, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
-                       k, min_support, 0, nbr, support, out, status);
+                       k, min_support, 0, 0, support_radius_h, nbr, support, out, status);
   else
     hipLaunchKernelGGL((k_mls_forward<false, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
-                       k, min_support, plane_iters, nbr, support, out, status);
+                       k, min_support, plane_iters, ball, support_radius_h, nbr, support, out,
+                       status);
   return hipGetLastError();
 }
 

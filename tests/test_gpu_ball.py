@@ -1,0 +1,132 @@
+"""GPU parity of the radius-R neighbourhood (``ball``: the k-nearest list
+entries within R = support_radius_h * h, the paper's neighbourhood of
+Section 1.4; TRUNCATED where the whole list lies inside R) against the FP64
+oracle on the same setting.
+
+Bars: statuses (with both flags) bit for bit (the FP32-moment path may take
+the OK / PLANE_ONLY pivot decision differently where the oracle's relative
+pivot is below 1e-5, which its FP32 moments do not resolve, on at most
+0.1 % of the points), FP64 path
+max |out - oracle| <= 1e-10 h with each point's error first divided by
+max(1, 1e-6 / p), p the oracle's smallest relative Cholesky pivot of the 6x6
+fit (small balls of a handful of points give fits with condition numbers up
+to ~1e9 just above the 1e-12 pivot rule, and the rounding error of a solve
+grows with the condition number); FP32-moment path RMS <= 1e-5 h over the
+points with p >= 1e-4, the others (at most 5 %) finite."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_03365_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_MAX_H = 1e-10
+FP32_RMS_H = 1e-5
+
+
+def api():
+    from paper_2401_03365_amd import api as a
+    return a
+
+
+def check(orc, P64, Q, k, h, out, st, precision, radius_h, iters=0):
+    ref_nbr, _ = orc.knn(P64, Q, k)
+    ref, ref_st, dg = orc.project(P64, Q, k, h, nbr=ref_nbr, ball=True,
+                                  support_radius_h=radius_h, plane_iters=iters, diag=True)
+    piv = np.where(np.isfinite(dg[:, 23]), dg[:, 23], 1.0)
+    # the FP32-moment path takes the pivot decision (OK or PLANE_ONLY) on its
+    # own moments, whose relative rounding (~1e-7) does not resolve a pivot
+    # below ~1e-5 of the largest diagonal: only there may it differ
+    differ = (st & 0x2F) != (ref_st & 0x2F)
+    if precision == "fp32":
+        pivot_call = (((st & 0x0F) | (ref_st & 0x0F)) == 2) & ((st & 0x20) == (ref_st & 0x20)) & \
+            (piv < 1e-5)
+        assert np.all(pivot_call[differ]), np.flatnonzero(differ & ~pivot_call)
+        assert differ.sum() <= 1e-3 * len(st)
+    else:
+        np.testing.assert_array_equal(st & 0x2F, ref_st & 0x2F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3) & ~differ
+    diff = np.abs(out.astype(np.float64) - ref)
+    if out.dtype == np.float32:
+        diff = np.maximum(diff - np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
+    if precision == "fp64":
+        cond = np.maximum(1.0, 1e-6 / np.maximum(piv, 1e-300))
+        err = (np.linalg.norm(diff, axis=1) / cond)[ok] / h
+        assert err.max() <= FP64_MAX_H, err.max()
+    else:
+        # FP32 moments (relative rounding ~1e-7) against a fit whose relative
+        # pivot is below 1e-4: the output is as uncertain as the fit is ill
+        # conditioned, so those points (a few per cent of small balls) are
+        # only required to be finite
+        well = piv >= 1e-4
+        assert np.all(np.isfinite(out[ok]))
+        assert (ok & ~well).sum() <= 0.05 * ok.sum()
+        err = np.linalg.norm(diff, axis=1)[ok & well] / h
+        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
+    return ref_st
+
+
+@pytest.mark.parametrize("radius_h", [1.3, 1.8, 3.0])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sphere_ball_matches_oracle(orc, precision, radius_h):
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    out, st = g.project(Pt.double(), 32, precision, ball=True, support_radius_h=radius_h)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    ref_st = check(orc, P64, P64, 32, h, out.cpu().numpy(), st.cpu().numpy(), precision,
+                   radius_h)
+    trunc = (ref_st & 0x20) != 0
+    # the radii span the regimes: mostly exact balls, mostly truncated lists
+    if radius_h == 1.3:
+        assert trunc.mean() < 0.05
+    if radius_h == 3.0:
+        assert trunc.mean() > 0.95
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_torus_with_outliers_ball_and_steps(orc, precision):
+    P = synth.torus(20000, sigma=0.005, n_outliers=200, seed=54)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    out, st = g.project(Pt, 40, precision, ball=True, support_radius_h=1.6, plane_iters=2)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    check(orc, P64, P64, 40, h, out.cpu().numpy(), st.cpu().numpy(), precision, 1.6, iters=2)
+
+
+def test_ball_changes_the_result(orc):
+    # the ball is not a no-op: against the k-nearest projection, off by far
+    # more than the tolerance where the ball is smaller than the list
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    o0, _ = g.project(Pt.double(), 32, "fp64")
+    o1, s1 = g.project(Pt.double(), 32, "fp64", ball=True, support_radius_h=1.5)
+    torch.cuda.synchronize()
+    assert (o1 - o0).norm(dim=1).max().item() > 1e-4 * h
+
+
+def test_heightfield_10m_ball(orc):
+    # full size, as one call over the whole cloud, sampled against the oracle
+    P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h, cell_size=1.25 * h)
+    rng = np.random.default_rng(26)
+    idx = np.sort(rng.choice(P.shape[0], 192, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    out, st = g.project(Pt.double(), 48, "fp32", ball=True, support_radius_h=1.8)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    check(orc, P64, P64[idx], 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(), "fp32",
+          1.8)
