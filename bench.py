@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--c4-n", type=int, default=2_000_000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the sphere quality table (radius-R neighbourhoods)")
     ap.add_argument("--plane-iters", type=int, default=3,
                     help="steps of the self-consistent reference plane in the extra "
                          "'plane_steps' measurement (0 skips it)")
@@ -392,6 +394,41 @@ def batch_fwd_bwd(api, torch, steps, warmup):
             "step": "search + fit + loss gradient + adjoint, one graph replay"}
 
 
+def quality_table(api, torch):
+    """The paper's quality protocol (Section 3.3 and its tables) on a
+    synthetic stand-in: a unit sphere of 200,000 points with Gaussian noise
+    sigma along the normal, projected once with the radius-R neighbourhood
+    (ball, at most the 64 nearest; the Gaussian width h = R / 3 so that the
+    ball is the 3h support), points with fewer than 3 neighbours within R
+    removed; deviation = | |out| - 1 | over the kept points."""
+    from paper_2401_03365_amd import synth
+    rows = []
+    for sigma in (0.005, 0.01, 0.03):
+        P = synth.sphere(200_000, sigma, seed=61)
+        Pt = torch.from_numpy(P).cuda()
+        dev_in = np.abs(np.linalg.norm(P.astype(np.float64), axis=1) - 1.0)
+        for R in (0.005, 0.01, 0.02, 0.03, 0.05):
+            h = R / 3.0
+            g = api.Grid(Pt, h)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out, st = g.project(Pt, 64, "fp32", ball=True, support_radius_h=3.0)
+            e1.record()
+            torch.cuda.synchronize()
+            out, st = out.cpu().numpy().astype(np.float64), st.cpu().numpy()
+            kept = (st & 0x0F) != 1
+            dev = np.abs(np.linalg.norm(out[kept], axis=1) - 1.0)
+            rows.append({"sigma": sigma, "R": R, "removed": int((~kept).sum()),
+                         "truncated": float(((st & 0x20) != 0).mean()),
+                         "mean": float(dev.mean()) if dev.size else None,
+                         "std": float(dev.std()) if dev.size else None,
+                         "min": float(dev.min()) if dev.size else None,
+                         "max": float(dev.max()) if dev.size else None,
+                         "input_mean": float(dev_in.mean()), "ms": e0.elapsed_time(e1)})
+            g.close()
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -497,6 +534,18 @@ def main():
             "fit_roofline": {"kernel": "k_mls_forward<fp32, steps>", "bound": "alu",
                              "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}}
+
+    if not args.no_quality:
+        t = time.perf_counter()
+        res["quality_sphere_200k"] = quality_table(api, torch)
+        best = {}
+        for row in res["quality_sphere_200k"]:
+            if row["mean"] is not None and (row["sigma"] not in best or
+                                            row["mean"] < best[row["sigma"]]["mean"]):
+                best[row["sigma"]] = row
+        log("quality (sphere 200k, ball): best R per sigma %s (%.1f s)" %
+            ({s_: (r["R"], round(r["mean"], 5), r["input_mean"]) for s_, r in best.items()},
+             time.perf_counter() - t))
 
     if not args.no_fwd_bwd:
         fb = {}
