@@ -64,7 +64,7 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_knn.argtypes = [P, i64, P, i64, i32, P, P]
         lib.orc_knn.restype = ctypes.c_int
-        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, i32, P, P, P]
+        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, i32, P, P, P, P]
         lib.orc_project.restype = ctypes.c_int
         lib.orc_grad_fd.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, P, f64, P, P]
         lib.orc_grad_fd.restype = ctypes.c_int
@@ -98,13 +98,16 @@ def knn(P, Q, k):
 
 
 def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=False,
-            plane_iters=0, ball=False):
+            plane_iters=0, ball=False, geometry=False):
     """One MLS projection pass. Returns (out (m,3) float64, status uint8 (m,)
     [, diag (m, 24)]). ``nbr`` are original indices (m, k); computed by brute
     force when omitted. ``plane_iters``: steps of the reference plane with the
     weights at the plane's own projection of the query (0: weights at r).
     ``ball``: the neighbourhood is the list entries within support_radius_h
-    * h (the paper's radius R); TRUNCATED flags a list wholly inside it."""
+    * h (the paper's radius R); TRUNCATED flags a list wholly inside it.
+    ``geometry``: also return (m, 5) = unit surface normal at the output
+    (sign that of the plane normal), mean and Gaussian curvature (after
+    ``diag`` when both are asked)."""
     lib = _load()
     P, Q = _c64(P), _c64(Q)
     m = Q.shape[0]
@@ -116,12 +119,14 @@ def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=Fals
     out = np.empty((m, 3), dtype=np.float64)
     st = np.empty(m, dtype=np.uint8)
     dg = np.empty((m, lib.orc_diag_stride()), dtype=np.float64) if diag else None
+    geo = np.empty((m, 5), dtype=np.float64) if geometry else None
     rc = lib.orc_project(_ptr(P), P.shape[0], _ptr(Q), m, int(k), float(h), _ptr(nbr),
                          float(support_radius_h), int(min_support), int(plane_iters),
-                         int(bool(ball)), _ptr(out), _ptr(st), _ptr(dg))
+                         int(bool(ball)), _ptr(out), _ptr(st), _ptr(dg), _ptr(geo))
     if rc:
         raise ValueError("orc_project failed (%d)" % rc)
-    return (out, st, dg) if diag else (out, st)
+    res = (out, st) + ((dg,) if diag else ()) + ((geo,) if geometry else ())
+    return res
 
 
 def grad_fd(P, Q, k, h, nbr, gout, rel_step=1e-6, support_radius_h=3.0, min_support=3):

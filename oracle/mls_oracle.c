@@ -54,6 +54,16 @@
  *       approximation g of the heights over H).
  *   O10 out = q + h * g(0,0) * n = q + h a_0 n (Section 2.1 and Algorithm 1:
  *       the projection of the point onto g is the result).
+ *   O11 (geometry, when asked) the MLS surface near q is the graph of g
+ *       over H, x -> q + h (x u + y v + g(x/h, y/h) n): at the output point
+ *       (the frame origin) its unit normal is N = (n - a_1 u - a_2 v) /
+ *       |n - a_1 u - a_2 v| (sign that of n, i.e. unoriented), with slopes
+ *       f_x = a_1, f_y = a_2 and second derivatives f_xx = 2 a_3 / h,
+ *       f_xy = a_4 / h, f_yy = 2 a_5 / h; W = 1 + f_x^2 + f_y^2; Gaussian
+ *       curvature K = (f_xx f_yy - f_xy^2) / W^2 and mean curvature
+ *       H = ((1 + f_y^2) f_xx - 2 f_x f_y f_xy + (1 + f_x^2) f_yy) /
+ *       (2 W^1.5), positive where the surface bends toward N. PLANE_ONLY:
+ *       N = n and no curvature (NaN); OUTLIER and NONFINITE: NaN.
  *   O12 gradient of out with respect to r and to the neighbours' positions,
  *       neighbour lists and statuses held fixed, by central finite differences
  *       with step 1e-6 * h.
@@ -260,9 +270,11 @@ static double plane_fit(const double *P, const double *r, const int32_t *nb, int
 /* O3-O10 for one query with a fixed neighbour list nb[0..k). */
 static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
                            int k, double h, const orc_consts *cs, double *out,
-                           double *dg) {
+                           double *dg, double *geo) {
   if (dg)
     for (int t = 0; t < ORC_DIAG; ++t) dg[t] = NAN;
+  if (geo)
+    for (int t = 0; t < 5; ++t) geo[t] = NAN;
   if (!finite3(r)) {
     out[0] = out[1] = out[2] = NAN;
     return ORC_PT_NONFINITE;
@@ -374,6 +386,8 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
     out[0] = q[0];
     out[1] = q[1];
     out[2] = q[2];
+    if (geo)
+      for (int a = 0; a < 3; ++a) geo[a] = nrm[a];
     return ORC_PT_PLANE_ONLY | flags;
   }
   double y6[6], a6[6];
@@ -392,6 +406,20 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
 
   /* O10 */
   for (int a = 0; a < 3; ++a) out[a] = q[a] + h * a6[0] * nrm[a];
+
+  /* O11 */
+  if (geo) {
+    double N[3];
+    for (int a = 0; a < 3; ++a) N[a] = nrm[a] - a6[1] * u[a] - a6[2] * v[a];
+    double nN = sqrt(dot3(N, N));
+    for (int a = 0; a < 3; ++a) geo[a] = N[a] / nN;
+    double fx = a6[1], fy = a6[2];
+    double fxx = 2.0 * a6[3] / h, fxy = a6[4] / h, fyy = 2.0 * a6[5] / h;
+    double W = 1.0 + fx * fx + fy * fy;
+    geo[3] = ((1.0 + fy * fy) * fxx - 2.0 * fx * fy * fxy + (1.0 + fx * fx) * fyy) /
+             (2.0 * W * sqrt(W));
+    geo[4] = (fxx * fyy - fxy * fxy) / (W * W);
+  }
   return ORC_PT_OK | flags;
 }
 
@@ -410,7 +438,8 @@ static void fill_consts(orc_consts *cs, double support_radius_h, int min_support
 int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
                 int32_t k, double h, const int32_t *nbr,
                 double support_radius_h, int32_t min_support, int32_t plane_iters,
-                int32_t ball, double *out, uint8_t *status, double *diag) {
+                int32_t ball, double *out, uint8_t *status, double *diag,
+                double *geo) {
   (void)n;
   if (k <= 0 || !(h > 0.0) || !isfinite(h) || plane_iters < 0) return 1;
   orc_consts cs;
@@ -418,7 +447,7 @@ int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t j = 0; j < m; ++j) {
     status[j] = project_one(P, Q + 3 * j, nbr + j * k, k, h, &cs, out + 3 * j,
-                            diag ? diag + ORC_DIAG * j : NULL);
+                            diag ? diag + ORC_DIAG * j : NULL, geo ? geo + 5 * j : NULL);
   }
   return 0;
 }
@@ -454,7 +483,7 @@ int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
       const double *g = gout + 3 * j;
       double r[3] = {Q[3 * j], Q[3 * j + 1], Q[3 * j + 2]};
       double o0[3];
-      uint8_t s0 = project_one(P, r, nb, k, h, &cs, o0, NULL);
+      uint8_t s0 = project_one(P, r, nb, k, h, &cs, o0, NULL, NULL);
       for (int a = 0; a < 3 * k; ++a) gl[a] = 0.0;
       /* local copy of the neighbour coordinates, indexed 0..k-1 */
       for (int t = 0; t < k; ++t) {
@@ -476,8 +505,8 @@ int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
         double rp[3] = {r[0], r[1], r[2]}, rm[3] = {r[0], r[1], r[2]};
         rp[a] += step;
         rm[a] -= step;
-        project_one(Pl, rp, loc, k, h, &cs, op, NULL);
-        project_one(Pl, rm, loc, k, h, &cs, om, NULL);
+        project_one(Pl, rp, loc, k, h, &cs, op, NULL, NULL);
+        project_one(Pl, rm, loc, k, h, &cs, om, NULL, NULL);
         gq[3 * j + a] = (g[0] * (op[0] - om[0]) + g[1] * (op[1] - om[1]) +
                          g[2] * (op[2] - om[2])) / (2.0 * step);
       }
@@ -485,9 +514,9 @@ int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
         for (int a = 0; a < 3; ++a) {
           double keep = Pl[3 * t + a];
           Pl[3 * t + a] = keep + step;
-          project_one(Pl, r, loc, k, h, &cs, op, NULL);
+          project_one(Pl, r, loc, k, h, &cs, op, NULL, NULL);
           Pl[3 * t + a] = keep - step;
-          project_one(Pl, r, loc, k, h, &cs, om, NULL);
+          project_one(Pl, r, loc, k, h, &cs, om, NULL, NULL);
           Pl[3 * t + a] = keep;
           gl[3 * t + a] = (g[0] * (op[0] - om[0]) + g[1] * (op[1] - om[1]) +
                            g[2] * (op[2] - om[2])) / (2.0 * step);
