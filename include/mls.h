@@ -256,6 +256,27 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params,
                        uint8_t *out_status, int32_t *out_neighbors,
                        void *workspace, size_t workspace_bytes, void *stream);
 
+/* mls_project plus the geometry of the MLS surface at each output point.
+ * Near q the surface is the graph of the fitted quadratic g over the plane H
+ * (Section 1.4 and Section 2.1): x -> q + h (x u + y v + g(x/h, y/h) n).
+ *   out_normals     nullable, n_queries x 3 in `dtype`: the graph's unit
+ *                   normal at the output, n - a_1 u - a_2 v normalised (its
+ *                   sign is that of the fitted plane's normal, which is not
+ *                   oriented).
+ *   out_curvatures  nullable, n_queries x 2 in `dtype`: mean curvature H
+ *                   (positive where the surface bends toward the returned
+ *                   normal) and Gaussian curvature K, in units of 1/length
+ *                   and 1/length^2 of the query coordinates.
+ * PLANE_ONLY: the plane's normal and NaN curvatures; OUTLIER and NONFINITE:
+ * NaN. Written by the fit stage (MLS_STAGE_FIT); the other arguments and
+ * errors are those of mls_project. */
+mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
+                                const void *queries, mls_dtype dtype, int64_t n_queries,
+                                const int64_t *query_offsets, void *out_points,
+                                uint8_t *out_status, int32_t *out_neighbors,
+                                void *out_normals, void *out_curvatures, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
 /* Bytes of device workspace mls_project_backward needs: the projection's
  * workspace plus a sorted-order accumulation buffer of 3 values per cloud
  * point (FP32 for MLS_PREC_FP32_MOMENTS, FP64 for MLS_PREC_FP64) (host).

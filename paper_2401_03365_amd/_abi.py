@@ -62,6 +62,8 @@ SIGNATURES = {
                           _SZ, _P]),
     "mls_project_backward": (_ST, [_P, ctypes.POINTER(MlsParams), _P, _ST, _I64, _P, _P, _P,
                                    _P, _P, _P, _SZ, _P]),
+    "mls_project_geometry": (_ST, [_P, ctypes.POINTER(MlsParams), _P, _ST, _I64, _P, _P, _P, _P,
+                                   _P, _P, _P, _SZ, _P]),
 }
 
 _lib = None

@@ -160,7 +160,8 @@ class Grid:
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
                 support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
                 status: Optional[torch.Tensor] = None, search_extra: int = 0,
-                refresh: bool = False, plane_iters: int = 0, ball: bool = False):
+                refresh: bool = False, plane_iters: int = 0, ball: bool = False,
+                geometry: bool = False):
         """One MLS projection pass. Returns (out, status[, neighbours]).
         ``stages``: 0 = search and fit, 1 = search only (lists stay in the
         grid's workspace), 2 = fit only from the preceding search.
@@ -171,7 +172,9 @@ class Grid:
         the plane's own projection of the query (0: weights at the query);
         ``ball``: the neighbourhood is the list entries within
         support_radius_h * h (the paper's radius R), status flag 0x20 where
-        the whole list lies inside it."""
+        the whole list lies inside it; ``geometry``: also return the surface
+        normal (n, 3) and the mean and Gaussian curvature (n, 2) at each
+        output, after the status: (out, status, normals, curvatures[, nbr])."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
         if refresh:
@@ -185,11 +188,23 @@ class Grid:
         nbr = torch.empty((n, k), dtype=torch.int32, device=self.device) if return_neighbors else None
         ws = self._proj_workspace(k + search_extra, n)
         qo, qo_p = _host_i64(query_offsets)
-        code = _abi.load().mls_project(self._handle, ctypes.byref(params), _ptr(queries),
-                                       _dtype_code(queries), n, qo_p, _ptr(out), _ptr(status),
-                                       _ptr(nbr), _ptr(ws), ws.numel(), _stream())
-        _abi.check(code, "mls_project")
-        return (out, status, nbr) if return_neighbors else (out, status)
+        if geometry:
+            normals = torch.empty((n, 3), dtype=queries.dtype, device=self.device)
+            curv = torch.empty((n, 2), dtype=queries.dtype, device=self.device)
+            code = _abi.load().mls_project_geometry(
+                self._handle, ctypes.byref(params), _ptr(queries), _dtype_code(queries), n, qo_p,
+                _ptr(out), _ptr(status), _ptr(nbr), _ptr(normals), _ptr(curv), _ptr(ws),
+                ws.numel(), _stream())
+            _abi.check(code, "mls_project_geometry")
+            res = (out, status, normals, curv)
+        else:
+            code = _abi.load().mls_project(self._handle, ctypes.byref(params), _ptr(queries),
+                                           _dtype_code(queries), n, qo_p, _ptr(out),
+                                           _ptr(status), _ptr(nbr), _ptr(ws), ws.numel(),
+                                           _stream())
+            _abi.check(code, "mls_project")
+            res = (out, status)
+        return res + (nbr,) if return_neighbors else res
 
     def project_backward(self, queries: torch.Tensor, grad_out: torch.Tensor, k: int,
                          precision: str = "fp32", neighbors: Optional[torch.Tensor] = None,

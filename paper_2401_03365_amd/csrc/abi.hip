@@ -462,10 +462,12 @@ mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries, mls_dty
   return MLS_OK;
 }
 
-mls_status mls_project(const mls_grid *grid, const mls_params *params, const void *queries,
-                       mls_dtype dtype, int64_t n_queries, const int64_t *query_offsets,
-                       void *out_points, uint8_t *out_status, int32_t *out_neighbors,
-                       void *workspace, size_t workspace_bytes, void *stream) {
+mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
+                                const void *queries, mls_dtype dtype, int64_t n_queries,
+                                const int64_t *query_offsets, void *out_points,
+                                uint8_t *out_status, int32_t *out_neighbors, void *out_normals,
+                                void *out_curvatures, void *workspace, size_t workspace_bytes,
+                                void *stream) {
   g_last_error[0] = 0;
   if (!params) return MLS_ERR_INVALID_ARGUMENT;
   if (params->precision != MLS_PREC_FP64 && params->precision != MLS_PREC_FP32_MOMENTS)
@@ -500,8 +502,17 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params, const voi
     MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
                                     params->min_support, params->plane_iters, params->ball,
                                     params->support_radius_h, nbr, support, out_points,
-                                    out_status, s));
+                                    out_status, out_normals, out_curvatures, s));
   return MLS_OK;
+}
+
+mls_status mls_project(const mls_grid *grid, const mls_params *params, const void *queries,
+                       mls_dtype dtype, int64_t n_queries, const int64_t *query_offsets,
+                       void *out_points, uint8_t *out_status, int32_t *out_neighbors,
+                       void *workspace, size_t workspace_bytes, void *stream) {
+  return mls_project_geometry(grid, params, queries, dtype, n_queries, query_offsets, out_points,
+                              out_status, out_neighbors, nullptr, nullptr, workspace,
+                              workspace_bytes, stream);
 }
 
 mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,

@@ -11,6 +11,11 @@
 // With ball = 1 every sum runs over the list entries whose canonical key to r
 // is at most (support_radius_h h)^2 (the paper's radius-R neighbourhood); a
 // list wholly inside that radius is flagged TRUNCATED.
+// Geometry (when asked): the graph q + h (x u + y v + g n) has at the output
+// the unit normal (n - a_1 u - a_2 v) / |.| and, with f_x = a_1, f_y = a_2,
+// f_xx = 2 a_3 / h, f_xy = a_4 / h, f_yy = 2 a_5 / h, W = 1 + f_x^2 + f_y^2,
+// the mean curvature ((1 + f_y^2) f_xx - 2 f_x f_y f_xy + (1 + f_x^2) f_yy) /
+// (2 W^1.5) and the Gaussian curvature (f_xx f_yy - f_xy^2) / W^2.
 //   frame   u, v orthonormal on the plane                    [Section 1.4]
 //   pass 2  e_i = d_i - <n,mu> n (= (p_i - q)/h), x = <u,e>, y = <v,e>,
 //           f = <n,e>, w'_i = exp(-|e_i|^2); 15 monomial sums + 6 sums of f
@@ -32,12 +37,30 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Normal (3 values) and curvatures (H, K) of query qi in the query dtype;
+// either array may be null.
+__device__ __forceinline__ void store_geometry(void *normals, void *curv, int is_f64, int64_t qi,
+                                               const double N[3], double H, double K) {
+  if (normals) store_vec(normals, is_f64, qi, N);
+  if (curv) {
+    if (is_f64) {
+      double *d = (double *)curv + 2 * qi;
+      d[0] = H; d[1] = K;
+    } else {
+      float *f = (float *)curv + 2 * qi;
+      f[0] = (float)H; f[1] = (float)K;
+    }
+  }
+}
+
 // kExt: the variant with plane steps and the ball neighbourhood (runtime
 // plane_iters and ball); the plain variant has neither.
 template <bool kF32, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv, int32_t k,
                                                         int32_t min_support, int32_t plane_iters,
                                                         int32_t ball, double support_radius_h,
+                                                        void *__restrict__ out_normals,
+                                                        void *__restrict__ out_curv,
                                                         const int32_t *__restrict__ nbr,
                                                         const uint8_t *__restrict__ support,
                                                         void *__restrict__ out,
@@ -52,12 +75,18 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     const double o[3] = {nanv, nanv, nanv};
     store_vec(out, qv.is_f64, qi, o);
     status[qi] = MLS_PT_NONFINITE;
+    if (kExt) store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
     return;
   }
   const int m = support[p];
   if (m < min_support) {
     store_vec(out, qv.is_f64, qi, r);
     status[qi] = MLS_PT_OUTLIER;
+    if (kExt) {
+      const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+      const double o[3] = {nanv, nanv, nanv};
+      store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+    }
     return;
   }
   const int cloud = qv.qcloud ? qv.qcloud[qi] : 0;
@@ -115,6 +144,23 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
   }
   store_vec(out, qv.is_f64, qi, o);
   status[qi] = st | pf.flags | extra_flags;
+  if (kExt && (out_normals || out_curv)) {
+    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+    double N[3] = {pf.n[0], pf.n[1], pf.n[2]};
+    double H = nanv, K = nanv;
+    if (full) {
+      for (int c = 0; c < 3; ++c) N[c] = pf.n[c] - a[1] * pf.u[c] - a[2] * pf.v[c];
+      const double nn = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+      for (int c = 0; c < 3; ++c) N[c] /= nn;
+      const double fx = a[1], fy = a[2];
+      const double fxx = 2.0 * a[3] / h, fxy = a[4] / h, fyy = 2.0 * a[5] / h;
+      const double W = 1.0 + fx * fx + fy * fy;
+      H = ((1.0 + fy * fy) * fxx - 2.0 * fx * fy * fxy + (1.0 + fx * fx) * fyy) /
+          (2.0 * W * sqrt(W));
+      K = (fxx * fyy - fxy * fxy) / (W * W);
+    }
+    store_geometry(out_normals, out_curv, qv.is_f64, qi, N, H, K);
+  }
 }
 
 }  // namespace
@@ -122,25 +168,28 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               int32_t precision, int32_t min_support, int32_t plane_iters,
                               int32_t ball, double support_radius_h, const int32_t *nbr,
-                              const uint8_t *support, void *out, uint8_t *status, hipStream_t s) {
+                              const uint8_t *support, void *out, uint8_t *status,
+                              void *out_normals, void *out_curvatures, hipStream_t s) {
   if (qv.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((qv.n + kBlock - 1) / kBlock);
   const bool f32 = precision == MLS_PREC_FP32_MOMENTS;
-  const bool ext = plane_iters != 0 || ball != 0;
+  const bool ext = plane_iters != 0 || ball != 0 || out_normals || out_curvatures;
   if (f32 && !ext)
     hipLaunchKernelGGL((k_mls_forward<true, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, 0, 0, support_radius_h, nbr, support, out, status);
+                       min_support, 0, 0, support_radius_h, nullptr, nullptr, nbr, support, out,
+                       status);
   else if (f32)
     hipLaunchKernelGGL((k_mls_forward<true, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, plane_iters, ball, support_radius_h, nbr, support, out,
-                       status);
+                       min_support, plane_iters, ball, support_radius_h, out_normals,
+                       out_curvatures, nbr, support, out, status);
   else if (!ext)
     hipLaunchKernelGGL((k_mls_forward<false, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
-                       k, min_support, 0, 0, support_radius_h, nbr, support, out, status);
+                       k, min_support, 0, 0, support_radius_h, nullptr, nullptr, nbr, support,
+                       out, status);
   else
     hipLaunchKernelGGL((k_mls_forward<false, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
-                       k, min_support, plane_iters, ball, support_radius_h, nbr, support, out,
-                       status);
+                       k, min_support, plane_iters, ball, support_radius_h, out_normals,
+                       out_curvatures, nbr, support, out, status);
   return hipGetLastError();
 }
 
