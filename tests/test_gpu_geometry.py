@@ -1,5 +1,6 @@
 """GPU parity of the surface geometry at the projected points (unit normal
-of the fitted graph, mean and Gaussian curvature) against the FP64 oracle.
+of the fitted graph, mean and Gaussian curvature) against the FP64 oracle,
+also for upsampling (queries four times denser than the samples).
 
 The normal's sign follows the fitted plane's normal, which is not oriented:
 normals are compared up to sign and H is compared after the same sign.
@@ -23,11 +24,15 @@ def api():
     return a
 
 
-def compare(orc, P, k, h, precision, res, **kw):
+def compare(orc, P, k, h, precision, res, Q=None, **kw):
     out, st, nrm, curv = (t.cpu().numpy().astype(np.float64) if t.dtype != torch.uint8
                           else t.cpu().numpy() for t in res)
     P64 = P.astype(np.float64)
-    ref, ref_st, geo = orc.project(P64, P64, k, h, geometry=True, **kw)
+    Q64 = P64 if Q is None else Q
+    ref, ref_st, geo = orc.project(P64, Q64, k, h, geometry=True, **kw)
+    if precision == "fp64":
+        okp = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+        assert (np.linalg.norm(out - ref, axis=1)[okp] / h).max() <= 1e-10
     np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
     # NaN patterns
     np.testing.assert_array_equal(np.isnan(nrm), np.isnan(geo[:, :3]))
@@ -61,8 +66,7 @@ def test_sphere_geometry(orc, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_torus_geometry_with_statuses_and_options(orc, precision):
-    # outliers (NaN geometry), FP32 queries and outputs, the plane steps and
-    # the ball neighbourhood together
+    # outliers (NaN geometry) and the plane steps together
     P = synth.torus(20000, sigma=0.005, n_outliers=200, seed=57)
     h = synth.mean_nn_h(P)
     g = api().Grid(torch.from_numpy(P).cuda(), h)
@@ -70,6 +74,21 @@ def test_torus_geometry_with_statuses_and_options(orc, precision):
                     plane_iters=2)
     torch.cuda.synchronize()
     compare(orc, P, 32, h, precision, res, plane_iters=2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_upsampling_queries(orc, precision):
+    # queries are not the samples: four per sample, jittered by up to 0.4 h
+    # (a denser set projected onto the surface of the sparse one)
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    rng = np.random.default_rng(59)
+    Q = (np.repeat(P.astype(np.float64), 4, axis=0) +
+         rng.uniform(-0.4, 0.4, (4 * P.shape[0], 3)) * h)
+    g = api().Grid(torch.from_numpy(P).cuda(), h)
+    res = g.project(torch.from_numpy(Q).cuda(), 32, precision, geometry=True)
+    torch.cuda.synchronize()
+    assert compare(orc, P, 32, h, precision, res, Q=Q) > 0.95 * Q.shape[0]
 
 
 def test_geometry_leaves_the_projection_unchanged(orc):
