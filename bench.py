@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--c4-n", type=int, default=2_000_000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-geometry", action="store_true",
+                    help="skip the geometry-output and upsampling measurement")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the sphere quality table (radius-R neighbourhoods)")
     ap.add_argument("--plane-iters", type=int, default=3,
@@ -394,6 +396,45 @@ def batch_fwd_bwd(api, torch, steps, warmup):
             "step": "search + fit + loss gradient + adjoint, one graph replay"}
 
 
+def geometry_and_upsampling(api, torch, pts, h, cell, k, reps=3):
+    """Fit with the surface geometry (normal, mean and Gaussian curvature at
+    each output) on the headline cloud, and upsampling: 4 queries per sample
+    jittered by up to 0.4 h, projected (search + fit) onto the cloud's
+    surface. Times from HIP events, inputs resident."""
+    n = pts.shape[0]
+    grid = api.Grid(pts, h, cell_size=cell)
+    q = pts.double()
+    out = torch.empty_like(q)
+    st = torch.empty((n,), dtype=torch.uint8, device=pts.device)
+    grid.project(q, k, "fp32", stages=1, out=out, status=st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    fit = timed(lambda: grid.project(q, k, "fp32", stages=2, out=out, status=st))
+    fit_geo = timed(lambda: grid.project(q, k, "fp32", stages=2, out=out, status=st,
+                                         geometry=True))
+    gen = torch.Generator(device=pts.device)
+    gen.manual_seed(71)
+    up = (q.repeat_interleave(4, dim=0) +
+          (torch.rand((4 * n, 3), generator=gen, device=pts.device, dtype=torch.float64) - 0.5)
+          * (0.8 * h))
+    up_ms = timed(lambda: grid.project(up, k, "fp32"))
+    grid.close()
+    return {"fit_ms": fit, "fit_geometry_ms": fit_geo,
+            "upsample_4x": {"n_queries": int(up.shape[0]), "ms": up_ms,
+                            "value": up.shape[0] / (up_ms / 1000.0), "unit": "pts/s",
+                            "step": "search + fit of 4 jittered queries per sample"}}
+
+
 def quality_table(api, torch):
     """The paper's quality protocol (Section 3.3 and its tables) on a
     synthetic stand-in: a unit sphere of 200,000 points with Gaussian noise
@@ -534,6 +575,13 @@ def main():
             "fit_roofline": {"kernel": "k_mls_forward<fp32, steps>", "bound": "alu",
                              "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}}
+
+    if not args.no_geometry:
+        res["geometry"] = geometry_and_upsampling(api, torch, pts, h, cell, args.k)
+        log("geometry: fit %.2f ms, with normals and curvatures %.2f ms; upsampling 4x: %.1f ms "
+            "(%.3g pts/s)" % (res["geometry"]["fit_ms"], res["geometry"]["fit_geometry_ms"],
+                              res["geometry"]["upsample_4x"]["ms"],
+                              res["geometry"]["upsample_4x"]["value"]))
 
     if not args.no_quality:
         t = time.perf_counter()
