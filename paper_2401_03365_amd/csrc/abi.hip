@@ -64,7 +64,11 @@ GridLayout grid_layout(int64_t n, int32_t c) {
 
 // Byte layout of the projection workspace.
 struct ProjLayout {
-  size_t nbr, support, qcloud, offsets, anchor, flag, total;
+  size_t nbr, support, qcloud, offsets, anchor, flag, order, total;
+  // the sort of queries that are not the grid's points, inside `anchor`
+  // (which the search writes only after the sort): two key buffers, one
+  // value buffer (the other one is `order`) and the radix sort's scratch
+  size_t skeys_a, skeys_b, svals, sradix;
 };
 
 // k_list: entries kept per query (k plus the search's extra neighbours).
@@ -77,8 +81,16 @@ ProjLayout proj_layout(int32_t n_clouds, int32_t k_list, int64_t n) {
   L.support = take((size_t)n);
   L.qcloud = take(n_clouds > 1 ? 4 * (size_t)n : 0);
   L.offsets = take(8 * ((size_t)n_clouds + 1));
-  L.anchor = take(32 * (size_t)n);  // per slot: the searched query and its bound
+  const size_t sort_bytes = 2 * align256(8 * (size_t)n) + align256(4 * (size_t)n) +
+                            align256(mls::radix_temp_bytes(n));
+  // per slot: the searched query and its bound
+  L.anchor = take(std::max(32 * (size_t)n, sort_bytes));
+  L.skeys_a = L.anchor;
+  L.skeys_b = L.skeys_a + align256(8 * (size_t)n);
+  L.svals = L.skeys_b + align256(8 * (size_t)n);
+  L.sradix = L.svals + align256(4 * (size_t)n);
   L.flag = take((size_t)n);         // per slot: left to a fresh search
+  L.order = take(4 * (size_t)n);    // per slot: the query it serves
   L.total = o;
   return L;
 }
@@ -394,7 +406,7 @@ namespace {
 // Shared validation and set-up of mls_knn / mls_project / mls_project_backward.
 mls_status prepare_queries(const mls_grid *grid, int32_t k, int32_t k_list, const void *queries,
                            mls_dtype dtype, int64_t n, const int64_t *query_offsets,
-                           void *workspace, size_t workspace_bytes, hipStream_t s,
+                           void *workspace, size_t workspace_bytes, bool sort, hipStream_t s,
                            mls::QueryView *qv, ProjLayout *L) {
   if (!grid || k < 1 || k > MLS_MAX_K || k_list < k || k_list > MLS_MAX_K || n < 0 ||
       n > 0x7fffffffll)
@@ -437,6 +449,25 @@ mls_status prepare_queries(const mls_grid *grid, int32_t k, int32_t k_list, cons
     MLS_HIP(mls::launch_fill_cloud_ids(off_dev, C, n, qcloud, s));
     qv->qcloud = qcloud;
   }
+  if (!aligned && n > 0) {
+    // other queries are processed in the Morton order of their cells; a
+    // search sorts them, and the stages that continue from a preceding
+    // search (fit only, refresh) keep that search's slots
+    int32_t *order = (int32_t *)(ws + L->order);
+    qv->order = order;
+    if (sort) {
+      // the value buffer the sort starts from is `order` when the number of
+      // 8-bit digit passes is even, so the result lands in `order` either way
+      const int passes = (g.key_bits + 7) / 8;
+      int32_t *svals = (int32_t *)(ws + L->svals);
+      int32_t *v0 = (passes & 1) ? svals : order, *v1 = (passes & 1) ? order : svals;
+      uint64_t *k0 = (uint64_t *)(ws + L->skeys_a), *k1 = (uint64_t *)(ws + L->skeys_b);
+      MLS_HIP(mls::launch_query_keys(queries, dtype == MLS_F64, n, qv->qcloud, g.clouds_dev,
+                                     g.view.morton_bits, k0, v0, s));
+      bool in_alt = false;  // = passes odd
+      MLS_HIP(mls::radix_sort_pairs(k0, v0, k1, v1, n, g.key_bits, ws + L->sradix, &in_alt, s));
+    }
+  }
   return MLS_OK;
 }
 
@@ -453,7 +484,7 @@ mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries, mls_dty
   mls::QueryView qv;
   ProjLayout L;
   mls_status st = prepare_queries(grid, k, k, queries, dtype, n_queries, query_offsets,
-                                  workspace, workspace_bytes, s, &qv, &L);
+                                  workspace, workspace_bytes, true, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
   char *ws = (char *)workspace;
   MLS_HIP(mls::launch_knn(grid->g.view, qv, k, k, 3.0, false, (int32_t *)(ws + L.nbr),
@@ -487,8 +518,11 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
   mls::QueryView qv;
   ProjLayout L;
   const int32_t k_list = params->k + params->search_extra;
+  // a fresh search sorts queries that are not the grid's points; refresh and
+  // fit-only calls keep the slots of the preceding search
+  const bool sort = (stages & MLS_STAGE_SEARCH) && !(stages & MLS_STAGE_REFRESH);
   mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
-                                  query_offsets, workspace, workspace_bytes, s, &qv, &L);
+                                  query_offsets, workspace, workspace_bytes, sort, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
@@ -546,7 +580,7 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   mls::QueryView qv;
   ProjLayout L;
   mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
-                                  query_offsets, workspace, workspace_bytes, s, &qv, &L);
+                                  query_offsets, workspace, workspace_bytes, !reuse, s, &qv, &L);
   if (st != MLS_OK) return st;
   if (((uintptr_t)workspace & 255) != 0) return MLS_ERR_INVALID_ARGUMENT;
   char *ws = (char *)workspace;

@@ -122,6 +122,38 @@ __global__ __launch_bounds__(kThreads) void k_keys(const float *__restrict__ pts
   }
 }
 
+// Keys of queries that are not the grid's points: the cloud id and the
+// Morton code of the query's cell in that cloud's grid (clamped to the grid,
+// so a query outside the box takes the nearest boundary cell); non-finite
+// queries sort last. Sorting the queries by these keys makes queries that
+// share cells and neighbours adjacent in the processing order, as the sorted
+// points are for queries aligned with them.
+template <typename Q>
+__global__ __launch_bounds__(kThreads) void k_query_keys(const Q *__restrict__ q, int64_t n,
+                                                         const int32_t *__restrict__ qcloud,
+                                                         const CloudDev *__restrict__ clouds,
+                                                         int32_t bits, uint64_t *__restrict__ keys,
+                                                         int32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double p[3] = {(double)q[3 * i], (double)q[3 * i + 1], (double)q[3 * i + 2]};
+  uint64_t key = kEmptyKey;
+  if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+    const int32_t c = qcloud ? qcloud[i] : 0;
+    const CloudDev &cd = clouds[c];
+    int32_t ic[3];
+    for (int a = 0; a < 3; ++a) {
+      // clamp in floating point: a far query's cell index may not fit an int
+      double t = floor((p[a] - cd.origin[a]) * cd.inv_cell);
+      t = t < 0.0 ? 0.0 : (t > (double)(cd.dims[a] - 1) ? (double)(cd.dims[a] - 1) : t);
+      ic[a] = (int32_t)t;
+    }
+    key = cell_key(c, ic[0], ic[1], ic[2], bits);
+  }
+  keys[i] = key;
+  vals[i] = (int32_t)i;
+}
+
 // ---- 3. radix sort --------------------------------------------------------------
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kThreads * kRsItems;  // 4096 keys per block
@@ -379,6 +411,20 @@ hipError_t launch_keys(const float *pts, const CloudDev *clouds, int32_t n_cloud
   if (gx > 4096) gx = 4096;
   hipLaunchKernelGGL(k_keys, dim3(gx, n_clouds), dim3(kThreads), 0, s, pts, clouds, bits, keys,
                      vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_keys(const void *q, bool is_f64, int64_t n, const int32_t *qcloud,
+                             const CloudDev *clouds, int32_t bits, uint64_t *keys, int32_t *vals,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(n, kThreads));
+  if (is_f64)
+    hipLaunchKernelGGL(k_query_keys<double>, grid, dim3(kThreads), 0, s, (const double *)q, n,
+                       qcloud, clouds, bits, keys, vals);
+  else
+    hipLaunchKernelGGL(k_query_keys<float>, grid, dim3(kThreads), 0, s, (const float *)q, n,
+                       qcloud, clouds, bits, keys, vals);
   return hipGetLastError();
 }
 

@@ -8,10 +8,11 @@
 // Keys of non-negative doubles order like their bit patterns.
 //
 // Work layout: one wavefront owns a chunk of consecutive queries in
-// processing order (Morton order of the grid for queries aligned with the
-// points), so consecutive queries usually fall in the same cell. The grid
-// indexes cells at several levels (edges c, 2c, 4c, 8c: a coarse cell is a
-// contiguous Morton range of the sorted points). For each query the wave
+// processing order (Morton order: the grid's order for queries aligned with
+// the points, a sort by cell key for other queries), so consecutive queries
+// usually fall in the same cell. The grid indexes cells at several levels
+// (edges c, 2c, 4c, 8c: a coarse cell is a contiguous Morton range of the
+// sorted points). For each query the wave
 // uses the 3x3x3 block of cells around the query's cell at a level chosen so
 // that the block both holds the k nearest and fits the candidate slots (the
 // level follows the previous query's k-th distance, so it adapts to the
@@ -653,7 +654,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       double x = 0.0, y = 0.0, z = 0.0;
       if (p < pend) {
         if (qv.aligned) qi = __float_as_int(g.pts[p].w);
-        else qi = qv.order ? qv.order[p] : (int32_t)p;
+        else qi = (int32_t)ordered_query(qv, p);
         if (qv.is_f64) {
           const double *q = (const double *)qv.q + 3 * (int64_t)qi;
           x = q[0]; y = q[1]; z = q[2];
@@ -942,7 +943,7 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
   if (p >= qv.n) return;
   int64_t qi;
   if (qv.aligned) qi = __float_as_int(g.pts[p].w);
-  else qi = qv.order ? qv.order[p] : p;
+  else qi = ordered_query(qv, p);
   double r[3];
   if (qv.is_f64) {
     const double *q = (const double *)qv.q + 3 * qi;
@@ -1048,7 +1049,7 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
       if (pending_only && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) != 2) continue;
       int64_t qi;
       if (qv.aligned) qi = __float_as_int(g.pts[p].w);
-      else qi = qv.order ? qv.order[p] : p;
+      else qi = ordered_query(qv, p);
       qi = __builtin_amdgcn_readfirstlane((int)qi);
       double r[3];
       if (qv.is_f64) {

@@ -131,7 +131,7 @@ __device__ __forceinline__ void store_vec(void *out, int is_f64, int64_t i, cons
 __device__ __forceinline__ int64_t query_of_slot(const GridView &g, const QueryView &qv,
                                                  int64_t p) {
   if (qv.aligned) return __float_as_int(g.pts[p].w);
-  return qv.order ? qv.order[p] : p;
+  return ordered_query(qv, p);
 }
 
 // Plane of the pass-1 moments: the weighted covariance, its smallest

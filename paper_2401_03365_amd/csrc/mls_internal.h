@@ -155,6 +155,9 @@ hipError_t launch_bbox(const float *pts, const int64_t *offsets_dev, int32_t n_c
 hipError_t launch_keys(const float *pts, const CloudDev *clouds, int32_t n_clouds,
                        int64_t max_cloud, int32_t bits, uint64_t *keys, int32_t *vals,
                        hipStream_t s);
+hipError_t launch_query_keys(const void *q, bool is_f64, int64_t n, const int32_t *qcloud,
+                             const CloudDev *clouds, int32_t bits, uint64_t *keys, int32_t *vals,
+                             hipStream_t s);
 size_t radix_temp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
                             int64_t n, int32_t key_bits, void *temp, bool *result_in_alt,
@@ -175,6 +178,15 @@ struct QueryView {
   int32_t aligned;          // queries aligned with points: order from the grid
   int32_t kstride;          // entries per query in the tile lists (k + search extra)
 };
+
+// Query index of slot p < qv.n for queries that are not the grid's points:
+// the permutation of the search's sort (clamped, like list entries, so that
+// a corrupted workspace cannot address outside the queries), or p.
+__device__ __forceinline__ int64_t ordered_query(const QueryView &qv, int64_t p) {
+  if (!qv.order) return p;
+  const uint32_t v = (uint32_t)qv.order[p];
+  return (int64_t)v < qv.n ? (int64_t)v : 0;
+}
 
 // Exact search of the k = qv.kstride nearest of every query into the tile
 // lists (the first kfit of each list are the kfit nearest), with the slot's
