@@ -217,6 +217,15 @@ mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
  * query i belongs to the cloud of point i) or, for one cloud, that every
  * query belongs to it.
  *
+ * Processing order: queries aligned with the points are processed in the
+ * grid's Morton order; other queries are first sorted by the key of their
+ * cell (cloud, Morton code), so that queries sharing cells and neighbours
+ * run together. The sort is part of every fresh search (mls_knn, a search
+ * without MLS_STAGE_REFRESH, the adjoint without reused lists); the stages
+ * that continue from a preceding search (MLS_STAGE_FIT alone,
+ * MLS_STAGE_REFRESH, the adjoint's reused lists) keep its order, which the
+ * workspace holds beside the lists. Results do not depend on the order.
+ *
  * Bytes of device workspace mls_project / mls_knn need for n_queries
  * queries with k neighbours kept per query (for mls_project and
  * mls_project_backward: params->k + params->search_extra) (host). */
