@@ -353,6 +353,50 @@ __device__ __forceinline__ void sort_lanes(uint64_t &mk, int32_t &mi, int32_t &m
   }
 }
 
+// Moves the kfit smallest (key, index) pairs of the lane entries (lanes
+// 0..ntop-1) to lanes 0..kfit-1 and the rest after them, each part in lane
+// order, and returns the largest key. A list that keeps extra entries needs
+// only this split: the fit takes its first kfit, and a refresh re-ranks the
+// whole list. The kfit smallest are found by the histogram selection, here
+// over the lane entries alone (about a third of the instructions of the
+// bitonic sort of the same 64 lanes).
+__device__ uint64_t partition_lanes(uint64_t &mk, int32_t &mi, int32_t &mp, int ntop, int kfit,
+                                    WaveLds &L, int lane) {
+  const bool valid = lane < ntop;
+  const uint64_t kmax = wave_max_u64(valid ? mk : 0ull);
+  if (ntop <= kfit) return kmax;
+  Slots t;
+  t.key[0] = valid ? mk : kEmptyKey;
+  t.idx[0] = mi;
+  t.pos[0] = mp;
+#pragma unroll
+  for (int i = 1; i < kSlots; ++i) {
+    t.key[i] = kEmptyKey;
+    t.idx[i] = 0x7fffffff;
+    t.pos[i] = 0;
+  }
+  const double mx = bitsd(kmax);
+  bool keep[kSlots];
+  uint32_t total;
+  select_topk(t, kfit, mx > 0.0 ? 255.0 / mx : 1.0, L, lane, keep, &total);
+  const uint64_t km = __ballot(keep[0]);
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const uint32_t dest = keep[0] ? popc(km & lt) : popc(km) + popc(~km & lt);
+  if (valid) {
+    L.ck[dest] = mk;
+    L.cpos[dest] = mp;
+    L.cidx[dest] = mi;
+  }
+  wave_sync();
+  if (valid) {
+    mk = L.ck[lane];
+    mp = L.cpos[lane];
+    mi = L.cidx[lane];
+  }
+  wave_sync();
+  return kmax;
+}
+
 template <int ctrl, int rows = 0xf>
 __device__ __forceinline__ void pair_max_step(uint64_t &mk, int32_t &mi) {
   const uint32_t lo = (uint32_t)mk, hi = (uint32_t)(mk >> 32);
@@ -837,9 +881,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       uint64_t mk = lane < ntop ? s.key[0] : kEmptyKey;
       int32_t mi = lane < ntop ? s.idx[0] : 0x7fffffff;
       int32_t mp = lane < ntop ? s.pos[0] : -1;
-      if (((kMode == kExtra || kMode == kFlagged) && k > kfit) ||
-          (kMode == kAny && (k > kfit || out_nbr || out_keys)))
+      // a list that keeps extra entries leads with the kfit nearest; lists
+      // returned to the caller are sorted
+      uint64_t klast = 0ull;
+      if ((kMode == kExtra || kMode == kFlagged) && k > kfit)
+        klast = partition_lanes(mk, mi, mp, ntop, kfit, L, lane);
+      if (kMode == kAny && (k > kfit || out_nbr || out_keys)) {
         sort_lanes(mk, mi, mp, lane);  // valid entries first
+        klast = readlane_u64(mk, k - 1);
+      }
       const bool valid = lane < ntop;
       const uint32_t m = popc(__ballot(valid && lane < kfit && bitsd(mk) <= rad2));
       // lists are stored per tile of 64 consecutive queries, neighbour-major:
@@ -869,9 +919,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
         }
         wave_sync();
       }
-      // the list is sorted when it keeps extra entries: its k-th key is in
-      // lane k - 1
-      const uint64_t kth = (kMode != kPlain && k > kfit) ? readlane_u64(mk, k - 1) : 0ull;
+      // the bound of a list with extra entries: its largest key (used when
+      // the list is full, ntop == k)
+      const uint64_t kth = klast;
       if (lane == 0) {
         support[p] = (uint8_t)((finite && ntop >= kfit) ? m : 0);
         double *an = anchor + 4 * p;
