@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
 // sqrt(bound) of the anchor, so a point outside it is at least
 // sqrt(bound) - |r - anchor| from the new query r (triangle inequality); when
 // the new kfit-th distance is below that, the kfit nearest are in the list
-// and the sorted list is final. Other slots are flagged for a fresh search.
+// and the re-ranked list is final. Other slots are flagged for a fresh search.
 __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, int32_t k,
                                                      int32_t kfit, double support_r_h,
                                                      int32_t *__restrict__ nbr,
@@ -1089,7 +1089,9 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
                                                      bool pending_only,
                                                      int32_t *__restrict__ out_nbr,
                                                      double *__restrict__ out_keys) {
+  __shared__ WaveLds lds[4];
   const int lane = threadIdx.x & 63;
+  WaveLds &L = lds[threadIdx.x >> 6];
   const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   for (int64_t task = blk * 4 + (threadIdx.x >> 6); task < nchunks;
@@ -1132,9 +1134,19 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
                          : kEmptyKey;
       int32_t mi = have ? __float_as_int(P.w) : 0x7fffffff;
       int32_t mp = have ? pos : -1;
-      sort_lanes(mk, mi, mp, lane);
-      const uint32_t nvalid = popc(__ballot(mk != kEmptyKey));
-      const uint64_t kth = readlane_u64(mk, kfit - 1);
+      const uint64_t vmask = __ballot(have);
+      const uint32_t nvalid = popc(vmask);
+      uint64_t kth, klast;
+      if (!out_nbr && !out_keys && vmask == (nvalid == 64 ? ~0ull : (1ull << nvalid) - 1)) {
+        // the list's entries lead (as the search writes them): split at kfit
+        klast = partition_lanes(mk, mi, mp, (int)nvalid, kfit, L, lane);
+        kth = wave_max_u64(lane < kfit && have ? mk : 0ull);
+      } else {
+        // sorted for the caller (or entries out of place)
+        sort_lanes(mk, mi, mp, lane);
+        kth = readlane_u64(mk, kfit - 1);
+        klast = readlane_u64(mk, k - 1);
+      }
       // certification (bound < 0: no usable list; +inf: the list is the cloud)
       bool ok = bound >= 0.0 && nvalid >= (uint32_t)kfit;
       if (ok && !isinf(bound)) {
@@ -1154,7 +1166,6 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
         }
         if (lane == 0) support[p] = (uint8_t)m;
       }
-      const uint64_t klast = readlane_u64(mk, k - 1);
       if (lane == 0) {
         slot_flag[p] = ok ? 0 : 1;
         // a slot left to the fresh search keeps, in place of its bound, the
