@@ -691,12 +691,19 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
     }
     const int64_t p0 = task * kChunk;
     const int64_t pend = min(p0 + kChunk, qv.n);
+    // the chunk's slots to search: all, or those a refresh left (one flag
+    // load per lane instead of one dependent load per slot)
+    uint64_t todo = ~0ull;
+    if (slot_flag) {
+      todo = __ballot(p0 + lane < pend && slot_flag[p0 + lane] != 0);
+      if (todo == 0) continue;
+    }
     {
       // lane j loads query slot p0 + j (one round trip for the chunk)
       const int64_t p = p0 + lane;
       int32_t qi = 0, cl = 0;
       double x = 0.0, y = 0.0, z = 0.0;
-      if (p < pend) {
+      if (p < pend && ((todo >> lane) & 1)) {
         if (qv.aligned) qi = __float_as_int(g.pts[p].w);
         else qi = (int32_t)ordered_query(qv, p);
         if (qv.is_f64) {
@@ -715,7 +722,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       wave_sync();
     }
     for (int64_t p = p0; p < pend; ++p) {
-      if (slot_flag && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) == 0) continue;
+      if (!((todo >> (p - p0)) & 1)) continue;
       if (slot_flag) {
         // the refresh left the squared kfit-th distance of the old list
         const double hint = anchor[4 * p + 3];
