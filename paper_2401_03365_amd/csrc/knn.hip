@@ -724,9 +724,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
     for (int64_t p = p0; p < pend; ++p) {
       if (!((todo >> (p - p0)) & 1)) continue;
       if (slot_flag) {
-        // the refresh left the squared kfit-th distance of the old list
+        // the refresh left the squared distance of the old list's farthest
+        // entry from the moved query (its k nearest lie within it); that
+        // bound is loose, so the block targets the smaller of it and the
+        // previous query's k-th distance
         const double hint = anchor[4 * p + 3];
-        if (hint > 0.0 && isfinite(hint)) rho_est = sqrt(hint);
+        if (hint > 0.0 && isfinite(hint))
+          rho_est = rho_est > 0.0 ? fmin(rho_est, sqrt(hint)) : sqrt(hint);
       }
       const int j = (int)(p - p0);
       const int64_t qi = __builtin_amdgcn_readfirstlane(Q.qi[j]);
@@ -1103,9 +1107,16 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   for (int64_t task = blk * 4 + (threadIdx.x >> 6); task < nchunks;
        task += (int64_t)gridDim.x * 4) {
-    const int64_t pend = min((task + 1) * kChunk, qv.n);
-    for (int64_t p = task * kChunk; p < pend; ++p) {
-      if (pending_only && __builtin_amdgcn_readfirstlane((int)slot_flag[p]) != 2) continue;
+    const int64_t p0 = task * kChunk;
+    const int64_t pend = min(p0 + kChunk, qv.n);
+    // the chunk's slots left by the lane pass (one flag load per lane)
+    uint64_t todo = ~0ull;
+    if (pending_only) {
+      todo = __ballot(p0 + lane < pend && slot_flag[p0 + lane] == 2);
+      if (todo == 0) continue;
+    }
+    for (int64_t p = p0; p < pend; ++p) {
+      if (!((todo >> (p - p0)) & 1)) continue;
       int64_t qi;
       if (qv.aligned) qi = __float_as_int(g.pts[p].w);
       else qi = ordered_query(qv, p);
