@@ -5,8 +5,9 @@ brute-force kNN over the whole cloud:
 
   torus 1,010,000 (1 % outliers), k = 32, FP32-moment and FP64 paths;
   height field 10,000,000, k = 48, 3 iterated FP32-moment passes (each pass
-      checked against the oracle fed the GPU's own pass input), and one
-      pass with 3 steps of the self-consistent reference plane;
+      checked against the oracle fed the GPU's own pass input), one pass
+      with 3 steps of the self-consistent reference plane, and 40,000,000
+      upsampling queries (positions, lists, geometry);
   bumped sphere 2,000,000, k = 32, FP32 forward and the adjoint (1,000
       queries against central finite differences);
   batch of 256 clouds, ~30M points, k = 32, FP32.
@@ -135,6 +136,45 @@ def test_heightfield_10m_plane_steps(orc):
     ok = (ref_st & 0x10) == 0
     err = np.linalg.norm(out[idx_t].cpu().numpy() - ref, axis=1)[ok] / h
     assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+
+
+def test_heightfield_10m_upsampling_40m(orc):
+    # 4 queries per sample jittered by up to 0.4 h (not the cloud's points:
+    # sorted by cell before the search), one call as timed, then once more
+    # with the lists and the geometry returned
+    P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h, cell_size=1.25 * h)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(71)
+    q = Pt.double()
+    up = (q.repeat_interleave(4, dim=0) +
+          (torch.rand((4 * q.shape[0], 3), generator=gen, device="cuda", dtype=torch.float64)
+           - 0.5) * (0.8 * h))
+    del q
+    rng = np.random.default_rng(27)
+    idx = np.sort(rng.choice(up.shape[0], 192, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    out, st = g.project(up, 48, "fp32")
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    Qs = up[idx_t].cpu().numpy()
+    ref_nbr, _ = orc.knn(P64, Qs, 48)
+    check_sample(orc, P64, Qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
+                 ref_nbr, "fp32")
+    out2, st2, nrm, curv, nbr = g.project(up, 48, "fp32", geometry=True, return_neighbors=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(nbr[idx_t].cpu().numpy(), ref_nbr)
+    assert torch.equal(st2, st)
+    _, ref_st, geo = orc.project(P64, Qs, 48, h, nbr=ref_nbr, geometry=True)
+    ok = ((ref_st & 0x0F) == 0) & ((ref_st & 0x10) == 0)
+    n_s = nrm[idx_t].cpu().numpy()[ok]
+    sgn = np.sign(np.sum(n_s * geo[ok, :3], axis=1))
+    dN = np.linalg.norm(n_s - sgn[:, None] * geo[ok, :3], axis=1)
+    dH = np.abs(curv[idx_t].cpu().numpy()[ok, 0] * sgn - geo[ok, 3]) * h
+    assert np.sqrt((dN ** 2).mean()) <= 1e-4 and np.sqrt((dH ** 2).mean()) <= 1e-3
 
 
 def test_bumped_sphere_2m_forward_and_adjoint(orc):
