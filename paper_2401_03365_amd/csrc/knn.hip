@@ -1218,6 +1218,16 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
   const int64_t tasks = (qv.n + kChunk - 1) / kChunk;
   int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 65536) blocks = 65536;
+  // launches that search or re-rank only the slots a refresh left take one
+  // resident grid (4 blocks per CU) looping over the chunks: with a block
+  // per chunk, the many chunks without such slots end at once and the
+  // dispatch of their blocks, not the work, sets the pace
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  const int64_t sparse_blocks = std::min<int64_t>(blocks, 4 * (int64_t)cus);
   if (refresh) {
     // lists that need no re-ranking are settled one lane per slot; sorted
     // output for the caller takes the re-ranking path for every slot
@@ -1225,8 +1235,9 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
     if (lane_pass)
       hipLaunchKernelGGL(k_knn_refresh_lane, dim3((unsigned)((qv.n + 255) / 256)), dim3(256), 0,
                          s, g, qv, k, kfit, support_r_h, nbr, support, anchor, flag);
-    hipLaunchKernelGGL(k_knn_refresh, dim3((unsigned)blocks), dim3(256), 0, s, g, qv, k, kfit,
-                       support_r_h, nbr, support, anchor, flag, lane_pass, out_nbr, out_keys);
+    hipLaunchKernelGGL(k_knn_refresh, dim3((unsigned)(lane_pass ? sparse_blocks : blocks)),
+                       dim3(256), 0, s, g, qv, k, kfit, support_r_h, nbr, support, anchor, flag,
+                       lane_pass, out_nbr, out_keys);
   }
   const bool own = !refresh && !out_nbr && !out_keys;
   if (own && k == kfit)
@@ -1236,7 +1247,7 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
     hipLaunchKernelGGL(k_knn<kExtra>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
                        qv, k, kfit, support_r_h, nbr, support, anchor, nullptr, nullptr, nullptr);
   else if (refresh && !out_nbr && !out_keys)
-    hipLaunchKernelGGL(k_knn<kFlagged>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s,
+    hipLaunchKernelGGL(k_knn<kFlagged>, dim3((unsigned)sparse_blocks), dim3(64 * kWavesPerBlock), 0, s,
                        g, qv, k, kfit, support_r_h, nbr, support, anchor, flag, nullptr, nullptr);
   else
     hipLaunchKernelGGL(k_knn<kAny>, dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, g,
