@@ -128,8 +128,8 @@ typedef struct {
  * previous search left in this workspace (same grid, k, search_extra, query
  * slots) are re-ranked by the canonical key for the new query positions. A
  * list holds every point within the distance R of the query it was searched
- * for (R = its last entry's distance), so when the new k-th distance is below
- * R minus the query's displacement, the k nearest are in the list (triangle
+ * for (R = its farthest entry's distance), so when the new k-th distance is
+ * below R minus the query's displacement, the k nearest are in the list (triangle
  * inequality) and the re-ranked list is the exact result; every other query
  * is searched afresh (every query when the previous search kept no extra
  * entries, search_extra = 0). The result is the same as a fresh search. */

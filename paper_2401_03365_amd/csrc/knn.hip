@@ -1187,9 +1187,8 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
       if (lane == 0) {
         slot_flag[p] = ok ? 0 : 1;
         // a slot left to the fresh search keeps, in place of its bound, the
-        // squared distance of the list's last entry for the new query: its k
-        // nearest lie within it, so the search can pick a block that
-        // certifies at once
+        // squared distance of the list's farthest entry from the new query:
+        // its k nearest lie within it, which steers the search's block
         if (!ok) anchor[4 * p + 3] = nvalid == (uint32_t)k ? bitsd(klast) : 0.0;
       }
     }
