@@ -117,3 +117,28 @@ def test_adjoint_reusing_the_search_on_unaligned_queries():
     assert (gp_fresh - gp_reuse).norm() <= 1e-5 * gp_fresh.norm()
     assert (gq_perm - gq_fresh[perm]).norm() <= 1e-4 * gq_fresh.norm()
     assert (gp_perm - gp_fresh).norm() <= 1e-4 * gp_fresh.norm()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 129])
+def test_small_unaligned_query_counts(orc, n):
+    # the sort of a handful of queries (single radix tiles, ragged last
+    # search tile), FP32 queries, lists bit for bit and the projection
+    P = synth.sphere(5000, 0.01, seed=97)
+    h = synth.mean_nn_h(P)
+    rng = np.random.default_rng(98 + n)
+    Q = (P[rng.choice(P.shape[0], n)].astype(np.float64) +
+         rng.uniform(-0.5, 0.5, (n, 3)) * h).astype(np.float32)
+    g = api().Grid(torch.from_numpy(P).cuda(), h)
+    nbr, keys = g.knn(torch.from_numpy(Q).cuda(), 16, return_keys=True)
+    out, st = g.project(torch.from_numpy(Q).cuda(), 16, "fp64")
+    torch.cuda.synchronize()
+    P64, Q64 = P.astype(np.float64), Q.astype(np.float64)
+    ref_idx, ref_key = orc.knn(P64, Q64, 16)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), ref_idx)
+    np.testing.assert_array_equal(keys.cpu().numpy(), ref_key)
+    ref, ref_st = orc.project(P64, Q64, 16, h, nbr=ref_idx)
+    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    diff = np.maximum(np.abs(out.cpu().numpy().astype(np.float64) - ref) -
+                      np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
+    assert (np.linalg.norm(diff, axis=1)[ok] / h).max() <= 1e-10
