@@ -301,15 +301,27 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   unsigned long long level_cells[mls::kMaxLevels] = {};
   STEP(hipMemcpyAsync(level_cells, counter, 8 * mls::kMaxLevels, hipMemcpyDeviceToHost, s));
   STEP(hipStreamSynchronize(s));
-  // every level shares one hash; drop coarse levels if they would not fit
+  // every level shares one hash, at a load factor of at most 1/8 where the
+  // reserved table allows (the search's lookups then probe about one slot)
+  // and never above 1/2 (coarse levels are dropped before that). The
+  // reservation, next_pow2(4 n) slots, holds twice the level-0 cells (at
+  // most n), so one level always fits; the check keeps every table write
+  // inside the reservation regardless.
   int n_levels = mls::kMaxLevels;
   while (bits - (n_levels - 1) < 1) --n_levels;
   uint64_t cap = 0;
   for (;; --n_levels) {
     uint64_t total = 0;
     for (int l = 0; l < n_levels; ++l) total += level_cells[l];
-    cap = next_pow2(std::max<uint64_t>(2 * total, 64));
-    if (cap <= L.table_cap_max || n_levels == 1) break;
+    const uint64_t need = next_pow2(std::max<uint64_t>(2 * total, 64));
+    if (need <= L.table_cap_max) {
+      cap = std::min<uint64_t>(next_pow2(std::max<uint64_t>(8 * total, 64)), L.table_cap_max);
+      break;
+    }
+    if (n_levels == 1) {
+      snprintf(g_last_error, sizeof g_last_error, "cell table exceeds its reservation");
+      return cleanup(MLS_ERR_WORKSPACE_TOO_SMALL);
+    }
   }
   const unsigned long long ncells = level_cells[0];
   STEP(mls::launch_build_table(skeys, n_points, n_levels, table, cap, s));
