@@ -55,6 +55,7 @@ PLANE_STEP_FLOPS = 34 + 3
 # distance holds 100-300 points on these surfaces).
 SEARCH_FP64_FLOPS_PER_QUERY = 200 * 10
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_knn_heightfield10M_k48.json")
+ISSUE_FILE = os.path.join(ROOT, "profiles", "valu_issue_heightfield10M_k48.json")
 SEARCH_SOURCES = [os.path.join(ROOT, "paper_2401_03365_amd", "csrc", f)
                   for f in ("knn.hip", "mls_internal.h")]
 
@@ -83,6 +84,21 @@ def search_traffic_bytes(args):
     kib = rec["fetch_kib_per_dispatch"] * rec["fetch_factor"] + \
         rec["write_kib_per_dispatch"] * rec["write_factor"]
     return kib * 1024.0
+
+
+def search_valu_busy(args):
+    """Fraction of the VALU issue capacity the full searches use, from the
+    recorded SQ_INSTS_VALU counter runs, or None when the kernel's source
+    changed since they were taken or the workload differs."""
+    try:
+        with open(ISSUE_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != search_source_hash() or rec.get("n") != args.n or \
+            rec.get("k") != args.k:
+        return None
+    return rec.get("valu_busy")
 
 
 def log(*a):
@@ -540,6 +556,9 @@ def main():
                 "traffic": search_traffic_bytes(args)}
         if roof["traffic"] is not None:
             roof["traffic_GBps"] = roof["traffic"] / (br32["search"] / 1000.0) / 1e9
+        # the search is bound by instruction issue: the share of the VALU
+        # pipes' issue cycles it fills (counters), beside the flop fraction
+        roof["valu_issue_busy"] = search_valu_busy(args)
 
     res = {"metric": METRIC, "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True,
