@@ -4,8 +4,9 @@ whole cloud), on sampled queries that the oracle computes one by one with
 brute-force kNN over the whole cloud:
 
   torus 1,010,000 (1 % outliers), k = 32, FP32-moment and FP64 paths;
-  height field 10,000,000, k = 48, 3 iterated FP32-moment passes (each pass
-      checked against the oracle fed the GPU's own pass input), one pass
+  height field 10,000,000, k = 48, 3 iterated passes, FP32-moment and FP64
+      paths (each pass checked against the oracle fed the GPU's own pass
+      input), one pass
       with 3 steps of the self-consistent reference plane, and 40,000,000
       upsampling queries (positions, lists, geometry);
   bumped sphere 2,000,000, k = 32, FP32 forward and the adjoint (1,000
@@ -89,7 +90,8 @@ def sampled_tile_sets(g, k_list, kfit, qidx):
     return torch.sort(orig[pos.view(-1, kfit).long()], dim=1).values.cpu().numpy()
 
 
-def test_heightfield_10m_three_passes(orc):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_heightfield_10m_three_passes(orc, precision):
     P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
     h = synth.mean_nn_h(P)
     a = api()
@@ -103,14 +105,14 @@ def test_heightfield_10m_three_passes(orc):
     for it in range(3):
         # as timed: the second search keeps 16 more, the third pass refreshes
         extra = 16 if it > 0 else 0
-        out, st = g.project(cur, 48, "fp32", search_extra=extra, refresh=it == 2)
+        out, st = g.project(cur, 48, precision, search_extra=extra, refresh=it == 2)
         torch.cuda.synchronize()
         sets = sampled_tile_sets(g, 48 + extra, 48, idx_t)
         qs = cur[idx_t].cpu().numpy()
         ref_nbr, _ = orc.knn(P64, qs, 48)
         np.testing.assert_array_equal(sets, np.sort(ref_nbr, axis=1))
         check_sample(orc, P64, qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
-                     ref_nbr, "fp32")
+                     ref_nbr, precision)
         cur = out
 
 
