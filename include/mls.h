@@ -349,8 +349,11 @@ size_t mls_autotune_workspace_bytes(int64_t n_points, int32_t n_clouds,
 
 /* Picks the cell edge factor f (cell = f * h of each cloud) with the fastest
  * neighbour search: for each candidate builds the grid and times (HIP events,
- * second of two runs) the search stage of k neighbours for every stride-th
- * point of each cloud as FP32 queries. Waits for the stream (host).
+ * second of two runs) the search stage of k neighbours for a sample of
+ * 1/stride of each cloud's points as FP32 queries: runs of 256 consecutive
+ * points of that grid's Morton order, one run in every 256 x stride, so that
+ * the sample meets the block reuse of a search over the whole cloud. Waits
+ * for the stream (host).
  *   points, n_points, cloud_offsets, n_clouds, h   as in mls_build_grid.
  *   candidates      host, n_candidates factors > 0.
  *   best_factor     host out: the fastest candidate.

@@ -255,8 +255,10 @@ class Grid:
 def autotune_cell_factor(points: torch.Tensor, h, k: int, cloud_offsets=None,
                          candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0),
                          stride: int = 16):
-    """Measures the neighbour search over every ``stride``-th point for each
-    candidate cell edge (factor x h) and returns (best factor, {factor: ms})."""
+    """Measures the neighbour search over a sample of 1/``stride`` of the
+    points (runs of 256 consecutive points of each candidate grid's Morton
+    order) for each candidate cell edge (factor x h) and returns
+    (best factor, {factor: ms})."""
     lib = _abi.load()
     _check_points(points, "points")
     n = points.shape[0]

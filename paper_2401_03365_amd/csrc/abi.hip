@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 
+#include "grid_access.h"
 #include "mls_internal.h"
 
 namespace {
@@ -142,6 +143,10 @@ mls_status check_async() {
 struct mls_grid {
   mls::GridHost g;
 };
+
+namespace mls {
+const GridHost &grid_host(const mls_grid *grid) { return grid->g; }
+}  // namespace mls
 
 extern "C" {
 

@@ -5,24 +5,33 @@
 // coarser levels or many cells, too large and every block holds too many
 // candidates. The best factor depends on k, on the surface's local dimension
 // and on the density spread, so it is measured: the grid is built with each
-// candidate edge and the search stage is timed over a strided sample of the
-// points. Uses only the public entry points plus one sampling kernel.
+// candidate edge and the search stage is timed over a sample of the points:
+// runs of 256 consecutive points of the grid's Morton order, one run in
+// every 256 x stride, so that the sampled queries meet the same block reuse
+// as a search over the whole cloud (a strided sample of the caller's order
+// spreads its queries stride times thinner and favours larger cells). Uses
+// the public entry points plus one sampling kernel.
 #include <math.h>
 #include <stdlib.h>
 
 #include <vector>
 
+#include "grid_access.h"
 #include "mls_internal.h"
 
 namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// out[t] = points[off[c] + (t - soff[c]) * stride] for the cloud c with
-// soff[c] <= t < soff[c + 1].
-__global__ void k_strided_sample(const float *__restrict__ pts, const int64_t *__restrict__ off,
-                                 const int64_t *__restrict__ soff, int32_t n_clouds,
-                                 int32_t stride, int64_t m, float *__restrict__ out) {
+constexpr int64_t kRun = 256;  // consecutive sorted points per sample run
+
+// Sample t of cloud c (soff[c] <= t < soff[c + 1]), i = t - soff[c]: the
+// sorted point at run i / kRun (one run every kRun * stride of the cloud's
+// finite points, wrapping at the end) and offset i % kRun; NaN for a cloud
+// without finite points.
+__global__ void k_run_sample(const float4 *__restrict__ spts, const mls::CloudDev *__restrict__ clouds,
+                             const int64_t *__restrict__ soff, int32_t n_clouds, int32_t stride,
+                             int64_t m, float *__restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m) return;
   int32_t lo = 0, hi = n_clouds - 1;
@@ -30,14 +39,22 @@ __global__ void k_strided_sample(const float *__restrict__ pts, const int64_t *_
     const int32_t mid = (lo + hi + 1) >> 1;
     if (soff[mid] <= t) lo = mid; else hi = mid - 1;
   }
-  const int64_t src = off[lo] + (t - soff[lo]) * (int64_t)stride;
-  out[3 * t + 0] = pts[3 * src + 0];
-  out[3 * t + 1] = pts[3 * src + 1];
-  out[3 * t + 2] = pts[3 * src + 2];
+  const mls::CloudDev &cd = clouds[lo];
+  const int64_t fin = cd.send - cd.sbegin;
+  float x = __int_as_float(0x7fc00000), y = x, z = x;
+  if (fin > 0) {
+    const int64_t i = t - soff[lo];
+    const int64_t pos = cd.sbegin + ((i / kRun) * kRun * (int64_t)stride + i % kRun) % fin;
+    const float4 P = spts[pos];
+    x = P.x; y = P.y; z = P.z;
+  }
+  out[3 * t + 0] = x;
+  out[3 * t + 1] = y;
+  out[3 * t + 2] = z;
 }
 
 struct TuneLayout {
-  size_t grid, sample, off, soff, proj, total;
+  size_t grid, sample, soff, proj, total;
 };
 
 TuneLayout tune_layout(int64_t n_points, int32_t n_clouds, int32_t k, int64_t m) {
@@ -46,7 +63,6 @@ TuneLayout tune_layout(int64_t n_points, int32_t n_clouds, int32_t k, int64_t m)
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
   L.grid = take(mls_grid_workspace_bytes(n_points, n_clouds));
   L.sample = take(12 * (size_t)m);
-  L.off = take(8 * ((size_t)n_clouds + 1));
   L.soff = take(8 * ((size_t)n_clouds + 1));
   L.proj = take(mls::proj_workspace_bytes(n_clouds, k, m));
   L.total = o;
@@ -102,16 +118,10 @@ mls_status mls_autotune_cell(const float *points, int64_t n_points, const int64_
   hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
   float *sample = (float *)(ws + L.sample);
-  int64_t *off_dev = (int64_t *)(ws + L.off);
   int64_t *soff_dev = (int64_t *)(ws + L.soff);
-  if (hipMemcpyAsync(off_dev, off.data(), 8 * off.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(soff_dev, soff.data(), 8 * soff.size(), hipMemcpyHostToDevice, s) !=
-          hipSuccess)
+  if (hipMemcpyAsync(soff_dev, soff.data(), 8 * soff.size(), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
     return MLS_ERR_HIP;
-  if (m > 0)
-    hipLaunchKernelGGL(k_strided_sample, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                       points, off_dev, soff_dev, n_clouds, stride, m, sample);
-  if (hipGetLastError() != hipSuccess) return MLS_ERR_HIP;
 
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return MLS_ERR_HIP;
@@ -138,6 +148,17 @@ mls_status mls_autotune_cell(const float *points, int64_t n_points, const int64_
     st = mls_build_grid(points, n_points, cloud_offsets, n_clouds, h, cell.data(), ws + L.grid,
                         L.sample - L.grid, stream, &grid);
     if (st != MLS_OK) break;
+    if (m > 0) {
+      // the sample follows this grid's Morton order
+      const mls::GridHost &gh = mls::grid_host(grid);
+      hipLaunchKernelGGL(k_run_sample, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                         gh.view.pts, gh.clouds_dev, soff_dev, n_clouds, stride, m, sample);
+      if (hipGetLastError() != hipSuccess) {
+        mls_grid_destroy(grid);
+        st = MLS_ERR_HIP;
+        break;
+      }
+    }
     float ms = 0.f;
     for (int rep = 0; rep < 2 && st == MLS_OK; ++rep) {  // the first run warms up
       if (hipEventRecord(e0, s) != hipSuccess) st = MLS_ERR_HIP;
