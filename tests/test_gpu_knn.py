@@ -114,3 +114,17 @@ def test_determinism():
     b, kb, _ = run_knn(P, P, 32, h, cell_size=2.0 * h)
     np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(ka, kb)
+
+
+@pytest.mark.parametrize("k", [1, 2, 63, 64])
+def test_k_extremes(orc, k):
+    # k from 1 to the 64 lanes of a wavefront (MLS_MAX_K), aligned queries
+    # (the cloud itself) and jittered ones (sorted by cell before the search)
+    P = synth.torus(8000, sigma=0.005, seed=105)
+    h = synth.mean_nn_h(P)
+    nbr, keys, _ = run_knn(P, P, k, h)
+    assert_lists_equal(orc, P, P, k, nbr, keys)
+    rng = np.random.default_rng(106)
+    Q = P[:3000].astype(np.float64) + rng.normal(0, 0.5 * h, (3000, 3))
+    nbr, keys, _ = run_knn(P, Q, k, h)
+    assert_lists_equal(orc, P, Q, k, nbr, keys)

@@ -285,3 +285,15 @@ def test_refresh_without_reranking_keeps_exact_sets(orc):
         err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
         assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
         cur = out
+
+
+@pytest.mark.parametrize("k", [4, 64])
+def test_projection_k_extremes(orc, k):
+    # k = 64 fills the wavefront; k = 4 leaves the quadratic fit without its
+    # six points (PLANE_ONLY where the support allows a plane)
+    P = synth.torus(8000, sigma=0.005, n_outliers=40, seed=107)
+    h = synth.mean_nn_h(P)
+    out, st = gpu_project(P, P.astype(np.float64), k, h, "fp64")
+    compare(orc, P, P.astype(np.float64), k, h, out, st, "fp64")
+    if k == 4:
+        assert np.all((st & 0x0F) != 0)
