@@ -6,7 +6,8 @@ gradient and the adjoint (reusing the search's lists) are captured in one
 graph and replayed several times, with eager work in between; every replay
 must reproduce the eager results (projection and query gradients bit for
 bit: same kernels, same inputs; point gradients to rounding, since their
-atomic summation order varies)."""
+atomic summation order varies). The same holds for queries that are not
+the cloud's points, whose captured search sorts them first."""
 import numpy as np
 import pytest
 import torch
@@ -112,3 +113,51 @@ def test_autotune_picks_a_measured_candidate():
     n2 = g2.knn(pts, 32)
     torch.cuda.synchronize()
     assert torch.equal(n1, n2)
+
+
+def test_graph_replay_with_unaligned_queries():
+    # queries that are not the cloud's points: the captured search sorts them
+    # (kernels only), the fit and the adjoint keep its slots; replays with
+    # other queries projected eagerly on the same grid in between
+    a = api()
+    P = synth.torus(30000, sigma=0.004, seed=34)
+    h = synth.mean_nn_h(P)
+    pts = torch.from_numpy(P).cuda()
+    g = a.Grid(pts, h)
+    rng = np.random.default_rng(35)
+    Q = np.repeat(P, 2, axis=0) + rng.uniform(-0.3, 0.3, (2 * P.shape[0], 3)).astype(np.float32) * h
+    q = torch.from_numpy(Q[rng.permutation(Q.shape[0])]).cuda()
+    k = 32
+    out = torch.empty_like(q)
+    status = torch.empty((q.shape[0],), dtype=torch.uint8, device="cuda")
+    gout = torch.from_numpy(rng.normal(size=Q.shape).astype(np.float32)).cuda()
+
+    def body():
+        g.project(q, k, "fp32", stages=1, out=out, status=status)
+        g.project(q, k, "fp32", stages=2, out=out, status=status)
+        return g.project_backward(q, gout, k, "fp32", reuse_lists=True)
+
+    gq_e, gp_e = body()
+    torch.cuda.synchronize()
+    out_e, st_e = out.clone(), status.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        body()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gq_g, gp_g = body()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        status.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, out_e), rep
+        assert torch.equal(status, st_e), rep
+        assert torch.equal(gq_g, gq_e), rep
+        assert (gp_g - gp_e).norm() <= 1e-5 * gp_e.norm(), rep
+        o2, s2 = g.project(q[: q.shape[0] // 3].flip(0).contiguous(), k, "fp32")
+        torch.cuda.synchronize()
