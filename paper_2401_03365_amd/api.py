@@ -290,13 +290,19 @@ def project(points: torch.Tensor, h, k: int, precision: str = "fp32", passes: in
             support_radius_h: float = 3.0):
     """Project a cloud onto its own MLS surface ``passes`` times (queries move,
     the cloud and its grid stay fixed). ``plane_iters``: steps of the
-    self-consistent reference plane per pass. Returns (out, status)."""
+    self-consistent reference plane per pass. From the second pass on, the
+    search keeps up to 16 extra neighbours and the passes after it refresh
+    those lists (exact; see MLS_STAGE_REFRESH) instead of searching every
+    query afresh. Returns (out, status)."""
     grid = Grid(points, h, cloud_offsets=cloud_offsets, cell_size=cell_size)
+    extra = min(16, _abi.MLS_MAX_K - k) if passes >= 3 else 0
     cur = points
     st = None
     for it in range(passes):
         out, st_new = grid.project(cur, k, precision, plane_iters=plane_iters, ball=ball,
-                                   support_radius_h=support_radius_h)
+                                   support_radius_h=support_radius_h,
+                                   search_extra=extra if it >= 1 else 0,
+                                   refresh=extra > 0 and it >= 2)
         if st is not None:
             frozen = (st & 0x0F) == _abi.PT_OUTLIER
             out[frozen] = cur[frozen]

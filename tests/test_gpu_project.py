@@ -297,3 +297,36 @@ def test_projection_k_extremes(orc, k):
     compare(orc, P, P.astype(np.float64), k, h, out, st, "fp64")
     if k == 4:
         assert np.all((st & 0x0F) != 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_top_level_passes_with_refresh(orc, precision):
+    # api.project refreshes the lists from the third pass on: the same
+    # results as plain passes up to the order of the list entries (the sums
+    # round differently): FP64 path within an FP32 ulp of the stored
+    # coordinates, FP32-moment path within the parity bar (RMS 1e-5 h);
+    # outliers stay frozen
+    P = synth.torus(20000, sigma=0.005, n_outliers=200, seed=108)
+    h = synth.mean_nn_h(P)
+    a = api()
+    Pt = torch.from_numpy(P).cuda()
+    out, st = a.project(Pt, h, 32, precision, passes=3)
+    g = a.Grid(Pt, h)
+    cur, sref = Pt, None
+    for it in range(3):
+        o, s = g.project(cur, 32, precision)
+        if sref is not None:
+            frozen = (sref & 0x0F) == 1
+            o[frozen] = cur[frozen]
+            s = torch.where(frozen, sref, s)
+        cur, sref = o, s
+    torch.cuda.synchronize()
+    o_np, r_np = out.cpu().numpy(), cur.cpu().numpy()
+    differ = (st != sref).cpu().numpy()
+    if precision == "fp64":
+        assert not differ.any()
+        assert np.all(np.abs(o_np - r_np) <= np.spacing(np.abs(r_np)))
+    else:
+        assert differ.mean() <= 1e-3
+        d = np.linalg.norm(o_np.astype(np.float64) - r_np, axis=1)[~differ] / h
+        assert np.sqrt((d ** 2).mean()) <= FP32_RMS_H
