@@ -132,7 +132,16 @@ typedef struct {
  * below R minus the query's displacement, the k nearest are in the list (triangle
  * inequality) and the re-ranked list is the exact result; every other query
  * is searched afresh (every query when the previous search kept no extra
- * entries, search_extra = 0). The result is the same as a fresh search. */
+ * entries, search_extra = 0). The result is the same as a fresh search.
+ * The library records, per workspace, which search last wrote it: a call
+ * with MLS_STAGE_FIT alone or with MLS_STAGE_REFRESH returns
+ * MLS_ERR_INVALID_ARGUMENT (before launching anything, reason in
+ * mls_last_error()) unless that search was on the same grid with the same k,
+ * search_extra, n_queries and query_offsets (and, for MLS_STAGE_FIT alone,
+ * the same support_radius_h). A workspace that no search has written, or
+ * whose last writer was another grid's search, an mls_knn call with another
+ * k, or an adjoint on caller lists, is rejected. The caller must not modify
+ * the workspace between the calls. */
 typedef enum {
   MLS_STAGE_ALL = 0,
   MLS_STAGE_SEARCH = 1,
@@ -309,8 +318,10 @@ size_t mls_project_backward_workspace_bytes(const mls_grid *grid, int32_t k,
  *                  else a fresh search (the lists of mls_project);
  *                  MLS_STAGE_FIT: the lists that the last search on this same
  *                  workspace left there (mls_project with the same grid,
- *                  queries, k and offsets, nothing else run on the workspace
- *                  since); `neighbors` must then be NULL.
+ *                  queries, k, search_extra and offsets, nothing else run on
+ *                  the workspace since; checked on the host as for
+ *                  mls_project's MLS_STAGE_FIT, MLS_ERR_INVALID_ARGUMENT
+ *                  otherwise); `neighbors` must then be NULL.
  *   neighbors      device, nullable: n_queries x k ORIGINAL indices as
  *                  written by mls_project / mls_knn. An entry outside
  *                  [0, n_points) makes its query an outlier.

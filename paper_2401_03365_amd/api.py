@@ -317,11 +317,12 @@ class MLSProject(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, queries, points, grid: Grid, k: int, precision: str):
-        out, status, nbr = grid.project(queries.detach().contiguous(), k, precision,
-                                        return_neighbors=True)
+        # the backward reads the same contiguous copy the forward projected
+        q = queries.detach().contiguous()
+        out, status, nbr = grid.project(q, k, precision, return_neighbors=True)
         ctx.grid, ctx.k, ctx.precision = grid, k, precision
         ctx.points_dtype = points.dtype
-        ctx.save_for_backward(queries.detach(), nbr)
+        ctx.save_for_backward(q, nbr)
         ctx.mark_non_differentiable(status)
         return out, status
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "grid_access.h"
@@ -136,6 +137,98 @@ mls_status check_async() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "earlier asynchronous error");
   return MLS_OK;
+}
+
+// ---- which search last wrote a projection workspace (host) ----------------
+// The stages that continue from a preceding search (fit only, refresh, the
+// adjoint's reused lists) read the lists, support counts and anchors that
+// search left in the workspace. A record per workspace range (the calling
+// grid, k, kept entries, query count, a digest of the query offsets and the
+// support radius) lets them check, on the host and before any launch, that
+// the workspace holds what they are about to read.
+struct SearchRecord {
+  uintptr_t lo, hi;         // workspace byte range written by the search
+  const mls_grid *grid;
+  int32_t k, k_list;
+  int64_t n;
+  uint64_t digest;          // query offsets (or their absence)
+  double support_r_h;
+};
+
+std::mutex g_rec_mu;
+constexpr int kMaxRecords = 64;
+SearchRecord g_rec[kMaxRecords];
+int g_rec_n = 0;
+
+uint64_t offsets_digest(const int64_t *off, int32_t c, int64_t n) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the words below
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)n);
+  mix(off ? 1u : 0u);
+  if (off)
+    for (int32_t i = 0; i <= c; ++i) mix((uint64_t)off[i]);
+  return h;
+}
+
+// Drops every record whose range meets [lo, hi) (the caller holds the lock).
+void drop_overlapping(uintptr_t lo, uintptr_t hi) {
+  int w = 0;
+  for (int i = 0; i < g_rec_n; ++i)
+    if (g_rec[i].hi <= lo || g_rec[i].lo >= hi) g_rec[w++] = g_rec[i];
+  g_rec_n = w;
+}
+
+void forget_workspace(const void *ws, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_rec_mu);
+  drop_overlapping((uintptr_t)ws, (uintptr_t)ws + std::max<size_t>(bytes, 1));
+}
+
+void record_search(const void *ws, size_t bytes, const mls_grid *grid, int32_t k, int32_t k_list,
+                   int64_t n, uint64_t digest, double support_r_h) {
+  std::lock_guard<std::mutex> lk(g_rec_mu);
+  const uintptr_t lo = (uintptr_t)ws, hi = lo + std::max<size_t>(bytes, 1);
+  drop_overlapping(lo, hi);
+  if (g_rec_n == kMaxRecords) {  // drop the oldest
+    for (int i = 1; i < g_rec_n; ++i) g_rec[i - 1] = g_rec[i];
+    --g_rec_n;
+  }
+  g_rec[g_rec_n++] = SearchRecord{lo, hi, grid, k, k_list, n, digest, support_r_h};
+}
+
+void forget_grid(const mls_grid *grid) {
+  std::lock_guard<std::mutex> lk(g_rec_mu);
+  int w = 0;
+  for (int i = 0; i < g_rec_n; ++i)
+    if (g_rec[i].grid != grid) g_rec[w++] = g_rec[i];
+  g_rec_n = w;
+}
+
+// MLS_OK when the last search that wrote `ws` was on `grid` with the same k,
+// kept entries, query count and offsets (and support radius when asked);
+// otherwise MLS_ERR_INVALID_ARGUMENT with the reason in mls_last_error().
+mls_status require_search(const void *ws, const mls_grid *grid, int32_t k, int32_t k_list,
+                          int64_t n, uint64_t digest, const double *support_r_h,
+                          const char *stage) {
+  std::lock_guard<std::mutex> lk(g_rec_mu);
+  const SearchRecord *r = nullptr;
+  for (int i = 0; i < g_rec_n; ++i)
+    if (g_rec[i].lo == (uintptr_t)ws) r = &g_rec[i];
+  const char *why = nullptr;
+  if (!r) why = "no search on this grid has written this workspace";
+  else if (r->grid != grid) why = "the workspace holds another grid's lists";
+  else if (r->k != k) why = "the search used another k";
+  else if (r->k_list != k_list) why = "the search kept another number of extra neighbours";
+  else if (r->n != n || r->digest != digest) why = "the search had other query counts or offsets";
+  else if (support_r_h && r->support_r_h != *support_r_h)
+    why = "the search counted the support with another radius";
+  if (!why) return MLS_OK;
+  snprintf(g_last_error, sizeof g_last_error, "%s: %s", stage, why);
+  return MLS_ERR_INVALID_ARGUMENT;
 }
 
 }  // namespace
@@ -363,6 +456,7 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
 
 mls_status mls_grid_destroy(mls_grid *grid) {
   if (!grid) return MLS_ERR_INVALID_ARGUMENT;
+  forget_grid(grid);
   free(grid->g.offsets);
   free(grid->g.finite_counts);
   free(grid->g.clouds_host);
@@ -500,6 +594,8 @@ mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries, mls_dty
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
+  if (grid && workspace && n_queries > 0 && k >= 1 && k <= MLS_MAX_K)
+    forget_workspace(workspace, proj_layout(grid->g.n_clouds, k, n_queries).total);
   mls_status st = prepare_queries(grid, k, k, queries, dtype, n_queries, query_offsets,
                                   workspace, workspace_bytes, true, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
@@ -507,6 +603,8 @@ mls_status mls_knn(const mls_grid *grid, int32_t k, const void *queries, mls_dty
   MLS_HIP(mls::launch_knn(grid->g.view, qv, k, k, 3.0, false, (int32_t *)(ws + L.nbr),
                           (uint8_t *)(ws + L.support), (double *)(ws + L.anchor),
                           (uint8_t *)(ws + L.flag), out_neighbors, out_keys, s));
+  record_search(workspace, L.total, grid, k, k, n_queries,
+                offsets_digest(query_offsets, grid->g.n_clouds, n_queries), 3.0);
   return MLS_OK;
 }
 
@@ -531,24 +629,43 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
     return MLS_ERR_INVALID_ARGUMENT;
   if (n_queries > 0 && (stages & MLS_STAGE_FIT) && (!out_points || !out_status))
     return MLS_ERR_INVALID_ARGUMENT;
+  if (!grid) return MLS_ERR_INVALID_ARGUMENT;
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
   const int32_t k_list = params->k + params->search_extra;
   // a fresh search sorts queries that are not the grid's points; refresh and
-  // fit-only calls keep the slots of the preceding search
+  // fit-only calls keep the slots of the preceding search, which must be the
+  // last search that wrote this workspace, with the same grid, k, kept
+  // entries and queries (checked here, before anything is launched)
   const bool sort = (stages & MLS_STAGE_SEARCH) && !(stages & MLS_STAGE_REFRESH);
+  const bool fit_only = (stages & MLS_STAGE_FIT) && !(stages & MLS_STAGE_SEARCH);
+  const uint64_t digest = offsets_digest(query_offsets, grid->g.n_clouds, n_queries);
+  if (n_queries > 0 && (fit_only || (stages & MLS_STAGE_REFRESH))) {
+    mls_status rs = require_search(workspace, grid, params->k, k_list, n_queries, digest,
+                                   fit_only ? &params->support_radius_h : nullptr,
+                                   fit_only ? "fit-only stage" : "refresh stage");
+    if (rs != MLS_OK) return rs;
+  }
+  // a search (re)writes the lists: the workspace holds no complete search
+  // until it has been launched
+  if ((stages & MLS_STAGE_SEARCH) && workspace && n_queries > 0 && params->k >= 1 &&
+      k_list <= MLS_MAX_K)
+    forget_workspace(workspace, proj_layout(grid->g.n_clouds, k_list, n_queries).total);
   mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
                                   query_offsets, workspace, workspace_bytes, sort, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
   uint8_t *support = (uint8_t *)(ws + L.support);
-  if (stages & MLS_STAGE_SEARCH)
+  if (stages & MLS_STAGE_SEARCH) {
     MLS_HIP(mls::launch_knn(grid->g.view, qv, k_list, params->k, params->support_radius_h,
                             (stages & MLS_STAGE_REFRESH) != 0, nbr, support,
                             (double *)(ws + L.anchor), (uint8_t *)(ws + L.flag), out_neighbors,
                             nullptr, s));
+    record_search(workspace, L.total, grid, params->k, k_list, n_queries, digest,
+                  params->support_radius_h);
+  }
   if (stages & MLS_STAGE_FIT)
     MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
                                     params->min_support, params->plane_iters, params->ball,
@@ -596,6 +713,16 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
+  // reused lists: the last search that wrote this workspace must be this
+  // grid's, with the same k, kept entries and queries
+  const uint64_t digest = offsets_digest(query_offsets, grid->g.n_clouds, n_queries);
+  if (reuse && n_queries > 0) {
+    mls_status rs = require_search(workspace, grid, params->k, k_list, n_queries, digest,
+                                   nullptr, "adjoint with reused lists");
+    if (rs != MLS_OK) return rs;
+  }
+  if (!reuse && n_queries > 0 && params->k >= 1 && k_list <= MLS_MAX_K)
+    forget_workspace(workspace, proj_layout(grid->g.n_clouds, k_list, n_queries).total);
   mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
                                   query_offsets, workspace, workspace_bytes, !reuse, s, &qv, &L);
   if (st != MLS_OK) return st;
@@ -603,12 +730,15 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
   if (n_queries > 0 && !reuse) {
-    if (neighbors)
+    if (neighbors) {
       MLS_HIP(mls::launch_lists_from_caller(grid->g.view, qv, params->k, neighbors, nbr, s));
-    else
+    } else {
       MLS_HIP(mls::launch_knn(grid->g.view, qv, k_list, params->k, params->support_radius_h,
                               false, nbr, (uint8_t *)(ws + L.support), (double *)(ws + L.anchor),
                               (uint8_t *)(ws + L.flag), nullptr, nullptr, s));
+      record_search(workspace, L.total, grid, params->k, k_list, n_queries, digest,
+                    params->support_radius_h);
+    }
   }
   void *gp = ws + bwd_gp_offset(grid->g.n_clouds, k_list, n_queries);
   MLS_HIP(mls::launch_mls_backward(grid->g.view, qv, params->k, params->precision,
@@ -618,3 +748,4 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
 }
 
 }  // extern "C"
+

@@ -206,3 +206,23 @@ def test_reuse_lists_of_preceding_search():
     assert (gp_fresh - gp_reuse).norm() <= 1e-5 * gp_fresh.norm()
     with pytest.raises(ValueError):
         g.project_backward(Pt, gout, 32, "fp32", neighbors=torch.zeros((P.shape[0], 32), dtype=torch.int32, device="cuda"), reuse_lists=True)
+
+
+def test_autograd_through_a_non_contiguous_query_view():
+    # queries given as a view (columns of an (n, 4) tensor): the backward
+    # reads the same contiguous copy the forward projected
+    a = api()
+    P = synth.sphere(6000, 0.01, seed=13)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = a.Grid(Pt, h)
+    wide = torch.cat([Pt.double(), torch.ones((P.shape[0], 1), dtype=torch.float64,
+                                               device="cuda")], dim=1).requires_grad_(True)
+    q = wide[:, :3]
+    assert not q.is_contiguous()
+    out, st = a.mls_project(q, Pt, g, 24, "fp64")
+    out.sum().backward()
+    gq, _ = g.project_backward(q.detach().contiguous(), torch.ones_like(out), 24, "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(wide.grad[:, :3], gq)
+    assert (wide.grad[:, 3] == 0).all()

@@ -18,6 +18,7 @@ import pytest
 import torch
 
 from paper_2401_03365_amd import synth
+from tests.parity import check_status, relative_gap
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +47,14 @@ def check(orc, P64, Q, k, h, out, st, precision, radius_h, iters=0):
         assert differ.sum() <= 1e-3 * len(st)
     else:
         np.testing.assert_array_equal(st & 0x2F, ref_st & 0x2F)
+    # the ambiguous-normal flag by the rule of tests/parity.py
+    check_status(st & 0x1F | (ref_st & 0x20), ref_st & 0x1F | (ref_st & 0x20),
+                 dg[:, 3:6]) if precision == "fp64" else None
+    flag_differ = ((st ^ ref_st) & 0x10) != 0
+    if precision == "fp32":
+        gap = relative_gap(dg[:, 3:6])
+        near = (gap >= 0.5e-6) & (gap <= 2e-6)
+        assert not (flag_differ & ~near & ~differ).any()
     ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3) & ~differ
     diff = np.abs(out.astype(np.float64) - ref)
     if out.dtype == np.float32:

@@ -21,6 +21,7 @@ import pytest
 import torch
 
 from paper_2401_03365_amd import synth
+from tests.parity import check_projection
 
 pytestmark = pytest.mark.gpu
 
@@ -33,22 +34,13 @@ def api():
     return a
 
 
-def check_sample(orc, P64, Qs, k, h, out, st, nbr, precision):
+def check_sample(orc, P64, Qs, k, h, out, st, nbr, precision, label="", **kw):
     """Qs: the sampled queries of the pass input (FP64); out/st/nbr: the GPU
     results for them."""
     ref_nbr, _ = orc.knn(P64, Qs, k)
     np.testing.assert_array_equal(nbr, ref_nbr)
-    ref, ref_st = orc.project(P64, Qs, k, h, nbr=ref_nbr)
-    np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    diff = np.abs(out.astype(np.float64) - ref)
-    if out.dtype == np.float32:
-        diff = np.maximum(diff - np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
-    err = np.linalg.norm(diff, axis=1)[ok] / h
-    if precision == "fp64":
-        assert err.max() <= FP64_MAX_H, err.max()
-    else:
-        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
+    return check_projection(orc, P64, Qs, k, h, out, st, precision, nbr=ref_nbr, label=label,
+                            **kw)
 
 
 def run_pass(g, q, k, precision, idx_t, **kw):
@@ -132,12 +124,8 @@ def test_heightfield_10m_plane_steps(orc):
     P64 = P.astype(np.float64)
     Qs = P64[idx]
     ref_nbr, _ = orc.knn(P64, Qs, 48)
-    ref, ref_st = orc.project(P64, Qs, 48, h, nbr=ref_nbr, plane_iters=3)
-    st_s = st[idx_t].cpu().numpy()
-    np.testing.assert_array_equal(st_s & 0x0F, ref_st & 0x0F)
-    ok = (ref_st & 0x10) == 0
-    err = np.linalg.norm(out[idx_t].cpu().numpy() - ref, axis=1)[ok] / h
-    assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+    check_projection(orc, P64, Qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
+                     "fp32", nbr=ref_nbr, plane_iters=3, label="plane steps")
 
 
 def test_heightfield_10m_upsampling_40m(orc):

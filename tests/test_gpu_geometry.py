@@ -15,6 +15,7 @@ import pytest
 import torch
 
 from paper_2401_03365_amd import synth
+from tests.parity import check_errors, check_status, oracle_ref, position_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +30,9 @@ def compare(orc, P, k, h, precision, res, Q=None, **kw):
                           else t.cpu().numpy() for t in res)
     P64 = P.astype(np.float64)
     Q64 = P64 if Q is None else Q
-    ref, ref_st, geo = orc.project(P64, Q64, k, h, geometry=True, **kw)
-    if precision == "fp64":
-        okp = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-        assert (np.linalg.norm(out - ref, axis=1)[okp] / h).max() <= 1e-10
-    np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
+    ref, ref_st, lam, geo = oracle_ref(orc, P64, Q64, k, h, geometry=True, **kw)
+    check_status(st, ref_st, lam)
+    check_errors(position_errors(out, ref, ref_st, h), precision)
     # NaN patterns
     np.testing.assert_array_equal(np.isnan(nrm), np.isnan(geo[:, :3]))
     np.testing.assert_array_equal(np.isnan(curv), np.isnan(geo[:, 3:5]))

@@ -1,8 +1,10 @@
 """GPU parity of the forward MLS projection against the FP64 oracle.
 
 Tolerances (in units of h, on points whose normal is not flagged ambiguous):
-FP64 path max |out - oracle| <= 1e-10 h; FP32-moment path RMS <= 1e-5 h.
-Statuses (low nibble) must match exactly."""
+FP64 path max |out - oracle| <= 1e-10 h; FP32-moment path RMS <= 1e-5 h and
+max <= 1e-4 h. Status bytes match, the ambiguous-normal flag included (it may
+differ only where the oracle's eigen-gap is within a factor 2 of the
+threshold); see tests/parity.py."""
 import json
 import os
 
@@ -11,6 +13,8 @@ import pytest
 import torch
 
 from paper_2401_03365_amd import synth
+from tests.parity import (FP32_MAX_H, check_errors, check_projection, check_status, oracle_ref,
+                          position_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,21 +37,11 @@ def gpu_project(P32, Q, k, h, precision, cell_size=None, return_neighbors=False)
     return tuple(r.cpu().numpy() for r in res)
 
 
-def compare(orc, P32, Q, k, h, out, st, precision):
+def compare(orc, P32, Q, k, h, out, st, precision, surface=True, label=""):
     """Outputs carry the query dtype; with FP32 outputs the storage rounding
     (half an FP32 ulp per coordinate) is added to the tolerance."""
-    ref, ref_st = orc.project(P32.astype(np.float64), np.asarray(Q, dtype=np.float64), k, h)
-    np.testing.assert_array_equal(st & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    diff = np.abs(out.astype(np.float64) - ref)
-    if out.dtype == np.float32:
-        diff = np.maximum(diff - np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
-    err = np.linalg.norm(diff, axis=1)[ok] / h
-    if precision == "fp64":
-        assert err.max() <= FP64_MAX_H, err.max()
-    else:
-        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
-    return err
+    return check_projection(orc, P32.astype(np.float64), np.asarray(Q, dtype=np.float64), k, h,
+                            out, st, precision, surface=surface, label=label)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -103,12 +97,8 @@ def test_iterated_passes_match_oracle_per_pass(orc):
     for it in range(3):
         out, st = g.project(cur, 48, "fp32")
         q = cur.cpu().numpy()
-        ref, ref_st = orc.project(P.astype(np.float64), q.astype(np.float64), 48, h)
-        stn = st.cpu().numpy()
-        np.testing.assert_array_equal(stn & 0x0F, ref_st & 0x0F)
-        ok = (ref_st & 0x10) == 0
-        err = np.linalg.norm(out.cpu().numpy().astype(np.float64) - ref, axis=1)[ok] / h
-        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+        check_projection(orc, P.astype(np.float64), q.astype(np.float64), 48, h,
+                         out.cpu().numpy(), st.cpu().numpy(), "fp32", label="pass %d" % it)
         cur = out
 
 
@@ -159,11 +149,8 @@ def test_iterated_passes_with_list_refresh(orc):
         q = cur.cpu().numpy()
         ref_nbr, _ = orc.knn(P64, q, 48)
         np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
-        ref, ref_st = orc.project(P64, q, 48, h, nbr=ref_nbr)
-        np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-        ok = (ref_st & 0x10) == 0
-        err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
-        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+        check_projection(orc, P64, q, 48, h, out.cpu().numpy(), st.cpu().numpy(), "fp32",
+                         nbr=ref_nbr, label="pass %d" % it)
         cur = out
 
 
@@ -184,11 +171,8 @@ def test_refresh_after_moves_is_exact(orc, shift_h):
                              search_extra=8, refresh=True)
     ref_nbr, _ = orc.knn(P.astype(np.float64), q1, 32)
     np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
-    ref, ref_st = orc.project(P.astype(np.float64), q1, 32, h, nbr=ref_nbr)
-    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
-    assert err.max() <= FP64_MAX_H
+    check_projection(orc, P.astype(np.float64), q1, 32, h, out.cpu().numpy(), st.cpu().numpy(),
+                     "fp64", nbr=ref_nbr, surface=False)
 
 
 def test_refresh_after_search_without_extras_is_exact(orc):
@@ -209,11 +193,8 @@ def test_refresh_after_search_without_extras_is_exact(orc):
                              refresh=True)
     ref_nbr, _ = orc.knn(P.astype(np.float64), q2, 32)
     np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
-    ref, ref_st = orc.project(P.astype(np.float64), q2, 32, h, nbr=ref_nbr)
-    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
-    assert err.max() <= FP64_MAX_H
+    check_projection(orc, P.astype(np.float64), q2, 32, h, out.cpu().numpy(), st.cpu().numpy(),
+                     "fp64", nbr=ref_nbr, surface=False)
 
 
 def test_search_extra_keeps_the_k_nearest_first(orc):
@@ -279,11 +260,8 @@ def test_refresh_without_reranking_keeps_exact_sets(orc):
         q = cur.cpu().numpy()
         ref_nbr, _ = orc.knn(P64, q, 48)
         np.testing.assert_array_equal(got, np.sort(ref_nbr, axis=1))
-        ref, ref_st = orc.project(P64, q, 48, h, nbr=ref_nbr)
-        np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-        ok = (ref_st & 0x10) == 0
-        err = np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h
-        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H
+        check_projection(orc, P64, q, 48, h, out.cpu().numpy(), st.cpu().numpy(), "fp32",
+                         nbr=ref_nbr, label="pass %d" % it)
         cur = out
 
 
@@ -294,7 +272,7 @@ def test_projection_k_extremes(orc, k):
     P = synth.torus(8000, sigma=0.005, n_outliers=40, seed=107)
     h = synth.mean_nn_h(P)
     out, st = gpu_project(P, P.astype(np.float64), k, h, "fp64")
-    compare(orc, P, P.astype(np.float64), k, h, out, st, "fp64")
+    compare(orc, P, P.astype(np.float64), k, h, out, st, "fp64", surface=k > 4)
     if k == 4:
         assert np.all((st & 0x0F) != 0)
 
@@ -330,3 +308,21 @@ def test_top_level_passes_with_refresh(orc, precision):
         assert differ.mean() <= 1e-3
         d = np.linalg.norm(o_np.astype(np.float64) - r_np, axis=1)[~differ] / h
         assert np.sqrt((d ** 2).mean()) <= FP32_RMS_H
+
+
+def test_ambiguous_flag_on_constructed_neighbourhoods(orc):
+    # the oracle's flag pins (isotropic stars, collinear sets, discs, gaps at
+    # 0.3 and 3 times the threshold) on both GPU paths: the status byte
+    # equals the oracle's, the flag included
+    from tests.test_oracle_flag import axis_star, line, numpy_gap, star_with_gap
+    cases = ([axis_star(0.5, 0.5, 0.5, s) for s in (0, 1, 2)] + [line(seed=s) for s in (0, 3)] +
+             [axis_star(0.2, 0.7, 0.7, s) for s in (0, 4)] +
+             [star_with_gap(g, s) for g in (0.3e-6, 3e-6) for s in (0, 5)])
+    q = np.zeros((1, 3))
+    for P in cases:
+        _, ref_st, lam = oracle_ref(orc, P.astype(np.float64), q, P.shape[0], 1.0)
+        gap = numpy_gap(P, q[0])
+        assert bool(ref_st[0] & 0x10) == (gap < 1e-6)
+        for precision in ("fp64", "fp32"):
+            out, st = gpu_project(P, q, P.shape[0], 1.0, precision)
+            assert st[0] == ref_st[0], (precision, gap, st[0], ref_st[0])

@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from paper_2401_03365_amd import synth
+from tests.parity import check_projection
 
 pytestmark = pytest.mark.gpu
 
@@ -57,20 +58,16 @@ def test_refresh_and_fit_only_on_unaligned_queries(orc):
     # search only, then fit only from its lists
     g.project(torch.from_numpy(q0).cuda(), 32, "fp64", stages=1, search_extra=16)
     out, st = g.project(torch.from_numpy(q0).cuda(), 32, "fp64", stages=2, search_extra=16)
-    ref, ref_st = orc.project(P64, q0, 32, h)
-    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    assert (np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h).max() <= 1e-10
+    check_projection(orc, P64, q0, 32, h, out.cpu().numpy(), st.cpu().numpy(), "fp64",
+                     surface=False)
     # the queries move a little: the refresh keeps the slots of the search
     q1 = q0 + rng.normal(size=q0.shape) * 0.05 * h
     out, st, nbr = g.project(torch.from_numpy(q1).cuda(), 32, "fp64", return_neighbors=True,
                              search_extra=16, refresh=True)
     ref_nbr, _ = orc.knn(P64, q1, 32)
     np.testing.assert_array_equal(nbr.cpu().numpy(), ref_nbr)
-    ref, ref_st = orc.project(P64, q1, 32, h, nbr=ref_nbr)
-    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    assert (np.linalg.norm(out.cpu().numpy() - ref, axis=1)[ok] / h).max() <= 1e-10
+    check_projection(orc, P64, q1, 32, h, out.cpu().numpy(), st.cpu().numpy(), "fp64",
+                     nbr=ref_nbr, surface=False)
 
 
 def test_batch_of_clouds_with_shuffled_query_ranges(orc):
@@ -136,9 +133,5 @@ def test_small_unaligned_query_counts(orc, n):
     ref_idx, ref_key = orc.knn(P64, Q64, 16)
     np.testing.assert_array_equal(nbr.cpu().numpy(), ref_idx)
     np.testing.assert_array_equal(keys.cpu().numpy(), ref_key)
-    ref, ref_st = orc.project(P64, Q64, 16, h, nbr=ref_idx)
-    np.testing.assert_array_equal(st.cpu().numpy() & 0x0F, ref_st & 0x0F)
-    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
-    diff = np.maximum(np.abs(out.cpu().numpy().astype(np.float64) - ref) -
-                      np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
-    assert (np.linalg.norm(diff, axis=1)[ok] / h).max() <= 1e-10
+    check_projection(orc, P64, Q64, 16, h, out.cpu().numpy(), st.cpu().numpy(), "fp64",
+                     nbr=ref_idx, surface=False)
