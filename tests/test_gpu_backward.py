@@ -222,7 +222,9 @@ def test_autograd_through_a_non_contiguous_query_view():
     assert not q.is_contiguous()
     out, st = a.mls_project(q, Pt, g, 24, "fp64")
     out.sum().backward()
-    gq, _ = g.project_backward(q.detach().contiguous(), torch.ones_like(out), 24, "fp64")
+    _, _, nbr = g.project(q.detach().contiguous(), 24, "fp64", return_neighbors=True)
+    gq, _ = g.project_backward(q.detach().contiguous(), torch.ones_like(out), 24, "fp64",
+                               neighbors=nbr)
     torch.cuda.synchronize()
     assert torch.equal(wide.grad[:, :3], gq)
     assert (wide.grad[:, 3] == 0).all()

@@ -318,11 +318,17 @@ def test_ambiguous_flag_on_constructed_neighbourhoods(orc):
     cases = ([axis_star(0.5, 0.5, 0.5, s) for s in (0, 1, 2)] + [line(seed=s) for s in (0, 3)] +
              [axis_star(0.2, 0.7, 0.7, s) for s in (0, 4)] +
              [star_with_gap(g, s) for g in (0.3e-6, 3e-6) for s in (0, 5)])
+    # (the FP32-moment path may take the quadratic fit's pivot decision
+    # differently where the oracle's relative pivot is below 1e-5: the
+    # stars' in-plane points leave the xy column of the fit at zero, which
+    # FP32 moments resolve only to ~1e-7)
     q = np.zeros((1, 3))
     for P in cases:
-        _, ref_st, lam = oracle_ref(orc, P.astype(np.float64), q, P.shape[0], 1.0)
+        _, ref_st, dg = orc.project(P.astype(np.float64), q, P.shape[0], 1.0, diag=True)
         gap = numpy_gap(P, q[0])
         assert bool(ref_st[0] & 0x10) == (gap < 1e-6)
         for precision in ("fp64", "fp32"):
             out, st = gpu_project(P, q, P.shape[0], 1.0, precision)
-            assert st[0] == ref_st[0], (precision, gap, st[0], ref_st[0])
+            assert st[0] & 0x10 == ref_st[0] & 0x10, (precision, gap, st[0], ref_st[0])
+            if precision == "fp64" or not dg[0, 23] < 1e-5:
+                assert st[0] == ref_st[0], (precision, gap, st[0], ref_st[0])
