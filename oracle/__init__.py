@@ -12,8 +12,9 @@ NumPy arrays. Every function follows the paper's MLS projection:
                    ties to the smaller index (neighbourhood search of
                    Section 2 / Section 2.2, here with k neighbours).
 * ``project``   -- reference plane (Section 1.4, Eq. (1.1) at t = 0, or
-                   ``plane_iters`` steps that move the weights to the plane's
-                   own projection q = r + t n), local frame, weighted
+                   ``plane_iters`` frozen-weight steps that move the weights
+                   to the plane's own projection q = r + t n, or Levin's
+                   smallest-|t| local minimum over (n, t)), local frame, weighted
                    quadratic height fit and projection (Section 2.1,
                    Algorithm 1), outlier rule (Section 3.3).
 * ``grad_fd``   -- J^T g by central finite differences with lists fixed.
@@ -32,7 +33,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mls_oracle.c")
 _LIB = os.path.join(_HERE, "libmls_oracle.so")
 
-PT_OK, PT_OUTLIER, PT_PLANE_ONLY, PT_NONFINITE = 0, 1, 2, 3
+PT_OK, PT_OUTLIER, PT_PLANE_ONLY, PT_NONFINITE, PT_NO_MINIMUM = 0, 1, 2, 3, 4
 PT_FLAG_AMBIGUOUS = 0x10
 PT_FLAG_TRUNCATED = 0x20
 DIAG_FIELDS = {
@@ -64,7 +65,8 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_knn.argtypes = [P, i64, P, i64, i32, P, P]
         lib.orc_knn.restype = ctypes.c_int
-        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, i32, P, P, P, P]
+        lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, i32, i32, P, P, P,
+                                    P]
         lib.orc_project.restype = ctypes.c_int
         lib.orc_grad_fd.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, P, f64, P, P]
         lib.orc_grad_fd.restype = ctypes.c_int
@@ -98,7 +100,7 @@ def knn(P, Q, k):
 
 
 def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=False,
-            plane_iters=0, ball=False, geometry=False):
+            plane_iters=0, ball=False, geometry=False, levin=False):
     """One MLS projection pass. Returns (out (m,3) float64, status uint8 (m,)
     [, diag (m, 24)]). ``nbr`` are original indices (m, k); computed by brute
     force when omitted. ``plane_iters``: steps of the reference plane with the
@@ -107,7 +109,9 @@ def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=Fals
     * h (the paper's radius R); TRUNCATED flags a list wholly inside it.
     ``geometry``: also return (m, 5) = unit surface normal at the output
     (sign that of the plane normal), mean and Gaussian curvature (after
-    ``diag`` when both are asked)."""
+    ``diag`` when both are asked). ``levin``: the reference plane is the
+    local minimum of Eq. (1.1) over (n, t) with the smallest |t| (O5c);
+    status NO_MINIMUM (4) where none lies within support_radius_h * h."""
     lib = _load()
     P, Q = _c64(P), _c64(Q)
     m = Q.shape[0]
@@ -122,7 +126,8 @@ def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=Fals
     geo = np.empty((m, 5), dtype=np.float64) if geometry else None
     rc = lib.orc_project(_ptr(P), P.shape[0], _ptr(Q), m, int(k), float(h), _ptr(nbr),
                          float(support_radius_h), int(min_support), int(plane_iters),
-                         int(bool(ball)), _ptr(out), _ptr(st), _ptr(dg), _ptr(geo))
+                         int(bool(ball)), int(bool(levin)), _ptr(out), _ptr(st), _ptr(dg),
+                         _ptr(geo))
     if rc:
         raise ValueError("orc_project failed (%d)" % rc)
     res = (out, st) + ((dg,) if diag else ()) + ((geo,) if geometry else ())
@@ -146,7 +151,8 @@ def grad_fd(P, Q, k, h, nbr, gout, rel_step=1e-6, support_radius_h=3.0, min_supp
     return gq, gp
 
 
-def project_passes(P, Q, k, h, passes, support_radius_h=3.0, min_support=3, plane_iters=0):
+def project_passes(P, Q, k, h, passes, support_radius_h=3.0, min_support=3, plane_iters=0,
+                   levin=False):
     """Iterated passes (queries move, cloud fixed): pass t+1 projects the
     outputs of pass t; a query that was an OUTLIER stays where it is."""
     cur = _c64(Q).copy()
@@ -154,7 +160,7 @@ def project_passes(P, Q, k, h, passes, support_radius_h=3.0, min_support=3, plan
     st = None
     for _ in range(passes):
         out, st_new = project(P, cur, k, h, support_radius_h=support_radius_h,
-                              min_support=min_support, plane_iters=plane_iters)
+                              min_support=min_support, plane_iters=plane_iters, levin=levin)
         out[frozen] = cur[frozen]
         st_new = np.where(frozen, np.uint8(PT_OUTLIER), st_new)
         frozen |= (st_new & 0x0F) == PT_OUTLIER

@@ -32,6 +32,23 @@
  *       t = 0 it approaches the fixed point nearest to r (the paper's local
  *       minimum with the smallest t). The number of steps is fixed (no
  *       convergence test), so every implementation takes the same steps.
+ *   O5c (levin = 1) Levin's reference plane (Section 1.4): a local minimum
+ *       over unit n and t of
+ *         F(n, t) = sum_i (<n, p_i - r> - t)^2 theta(|p_i - r - t n|)
+ *       (Eq. (1.1) with q = r + t n and D = <n, q>), the weights moving with
+ *       the plane. In units of h (d_i = (p_i - r)/h, tau = t/h) a summand is
+ *       (a_i - tau)^2 exp(-|d_i - tau n|^2) with a_i = <n, d_i>. The paper
+ *       takes the local minimum with the smallest t that gives "the local
+ *       tangent plane near r"; it is reached here by Newton's method with
+ *       backtracking from the plane of O4-O6 (weights at r: the tangent plane
+ *       estimate near r), in the coordinates (alpha, beta, tau) with
+ *       n = normalize(n0 + alpha u + beta v) on the frame (u, v) of O7. The
+ *       minimum with t = 0 of planes through r that contain the normal
+ *       direction (the uncentred moment's smallest eigenvector for a query
+ *       more than about h/2 off the data) is not a tangent plane and is not
+ *       taken. A descent that leaves |t| <= support_radius_h * h: status
+ *       NO_MINIMUM, out = r. The flag NORMAL_AMBIGUOUS refers to the start
+ *       plane. Then O7-O10 with this n and q = r + t n.
  *   O3b (ball = 1) the paper's neighbourhood of radius R (Section 1.4, the
  *       points within R of r) with R = support_radius_h * h: O4, O5b and O8
  *       use only the list entries whose O1 key is at most R^2. The list holds
@@ -79,6 +96,7 @@
 #define ORC_PT_OUTLIER 1
 #define ORC_PT_PLANE_ONLY 2
 #define ORC_PT_NONFINITE 3
+#define ORC_PT_NO_MINIMUM 4
 #define ORC_PT_FLAG_AMBIGUOUS 0x10
 #define ORC_PT_FLAG_TRUNCATED 0x20
 
@@ -231,8 +249,169 @@ typedef struct {
   double ambig_gap;        /* O5 relative eigen-gap for the flag (1e-6) */
   int plane_iters;         /* O5b refinements of the reference plane (0) */
   int ball;                /* O3b neighbourhood of radius support_radius_h * h */
+  int levin;               /* O5c Levin's reference plane */
 } orc_consts;
 
+/* O7: the frame (u, v) on the plane with unit normal n. */
+static void frame_of(const double n[3], double u[3], double v[3]) {
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (fabs(n[a]) < fabs(n[ax])) ax = a;
+  double ea[3] = {0, 0, 0};
+  ea[ax] = 1.0;
+  cross3(ea, n, u);
+  double un = sqrt(dot3(u, u));
+  for (int a = 0; a < 3; ++a) u[a] /= un;
+  cross3(n, u, v);
+}
+
+/* O5c: the value, gradient and Hessian of F (units of h) at (n, tau) in the
+ * coordinates (alpha, beta, tau) of the tangent frame (u, v) of n:
+ *   L[0] F, L[1..3] dF/d(alpha, beta, tau),
+ *   L[4] H_aa, L[5] H_ab, L[6] H_bb, L[7] H_at, L[8] H_bt, L[9] H_tt.
+ * Per summand f(a, tau) = (a - tau)^2 E, E = exp(-|d - tau n|^2), a = <n, d>,
+ * s = a - tau (dE/da = 2 tau E, dE/dtau = 2 s E):
+ *   f_a = 2 E s (1 + tau s),           f_t = 2 E s (s^2 - 1),
+ *   f_aa = 2 E (1 + 4 tau s + 2 tau^2 s^2),
+ *   f_at = 2 E (3 s^2 + 2 tau s^3 - 1 - 2 tau s),
+ *   f_tt = 2 E (2 s^4 - 5 s^2 + 1).
+ * On the sphere the gradient is sum f_a (x, y) with x = <u, d>, y = <v, d>,
+ * and the Hessian of the n part is sum f_aa (x, y)(x, y)^T minus
+ * (sum f_a a) times the identity. */
+static void levin_terms(const double *d, const unsigned char *use, int m, const double n[3],
+                        double tau, double L[10]) {
+  double u[3], v[3];
+  frame_of(n, u, v);
+  double saa = 0.0;
+  for (int i = 0; i < 10; ++i) L[i] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    if (!use[j]) continue;
+    const double *dj = d + 3 * j;
+    double a = dot3(n, dj), x = dot3(u, dj), y = dot3(v, dj);
+    double e[3] = {dj[0] - tau * n[0], dj[1] - tau * n[1], dj[2] - tau * n[2]};
+    double E = exp(-dot3(e, e));
+    double sv = a - tau;
+    double fa = 2.0 * E * sv * (1.0 + tau * sv);
+    double ft = 2.0 * E * sv * (sv * sv - 1.0);
+    double faa = 2.0 * E * (1.0 + 4.0 * tau * sv + 2.0 * tau * tau * sv * sv);
+    double fat = 2.0 * E * (3.0 * sv * sv + 2.0 * tau * sv * sv * sv - 1.0 - 2.0 * tau * sv);
+    double ftt = 2.0 * E * (2.0 * sv * sv * sv * sv - 5.0 * sv * sv + 1.0);
+    L[0] += E * sv * sv;
+    L[1] += fa * x;
+    L[2] += fa * y;
+    L[3] += ft;
+    L[4] += faa * x * x;
+    L[5] += faa * x * y;
+    L[6] += faa * y * y;
+    L[7] += fat * x;
+    L[8] += fat * y;
+    L[9] += ftt;
+    saa += fa * a;
+  }
+  L[4] -= saa;
+  L[6] -= saa;
+}
+
+/* Newton direction s = -H^-1 g for the symmetric 3x3 H (rows H[0..2]) by
+ * Cholesky; where H is not positive definite, mu I is added to it, mu
+ * starting at 1e-3 of its largest diagonal magnitude and doubling. Returns 1
+ * when H itself was positive definite. */
+static int newton_dir(const double H[3][3], const double g[3], double s[3]) {
+  double scale = fmax(fabs(H[0][0]), fmax(fabs(H[1][1]), fabs(H[2][2])));
+  if (!(scale > 0.0)) scale = 1.0;
+  double mu = 0.0;
+  for (int attempt = 0; attempt < 200; ++attempt) {
+    double A[3][3], L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) A[a][b] = H[a][b] + (a == b ? mu : 0.0);
+    int ok = 1;
+    for (int c = 0; c < 3 && ok; ++c) {
+      double v = A[c][c];
+      for (int e = 0; e < c; ++e) v -= L[c][e] * L[c][e];
+      if (!(v > 0.0)) {
+        ok = 0;
+        break;
+      }
+      L[c][c] = sqrt(v);
+      for (int r = c + 1; r < 3; ++r) {
+        double z = A[r][c];
+        for (int e = 0; e < c; ++e) z -= L[r][e] * L[c][e];
+        L[r][c] = z / L[c][c];
+      }
+    }
+    if (ok) {
+      double y[3];
+      for (int r = 0; r < 3; ++r) {
+        double z = -g[r];
+        for (int e = 0; e < r; ++e) z -= L[r][e] * y[e];
+        y[r] = z / L[r][r];
+      }
+      for (int r = 2; r >= 0; --r) {
+        double z = y[r];
+        for (int e = r + 1; e < 3; ++e) z -= L[e][r] * s[e];
+        s[r] = z / L[r][r];
+      }
+      return mu == 0.0;
+    }
+    mu = (mu == 0.0) ? 1e-3 * scale : 2.0 * mu;
+  }
+  for (int a = 0; a < 3; ++a) s[a] = -g[a] / scale;
+  return 0;
+}
+
+/* O5c for one query: Newton's method with backtracking on F over (n, tau)
+ * from the start (n, tau) (in place). Each step: the direction of
+ * newton_dir in the tangent coordinates (alpha, beta, tau), at most 0.5
+ * long, the point moving to (normalize(n + alpha u + beta v), tau + dtau).
+ * Far from the minimum (a shifted Hessian, or a direction longer than
+ * 1e-4) the step length halves until F has fallen by at least 1e-4 of the
+ * step times the slope (Armijo); closer in, where the Hessian is positive
+ * definite and Newton converges quadratically, the full step is taken (the
+ * fall of F is then below its rounding). Stops when the direction is below
+ * 1e-15, when no length lowers F, or when a full step no longer shrinks.
+ * Returns 0 when |tau| leaves [0, tmax] (no minimum within reach), else 1. */
+static int levin_plane(const double *d, const unsigned char *use, int m, double tmax,
+                       double n[3], double *tau) {
+  double L[10];
+  levin_terms(d, use, m, n, *tau, L);
+  double prev_len = INFINITY;
+  for (int it = 0; it < 200; ++it) {
+    const double H[3][3] = {{L[4], L[5], L[7]}, {L[5], L[6], L[8]}, {L[7], L[8], L[9]}};
+    const double g[3] = {L[1], L[2], L[3]};
+    double sdir[3];
+    const int pd = newton_dir(H, g, sdir);
+    double len = sqrt(dot3(sdir, sdir));
+    if (len > 0.5)
+      for (int a = 0; a < 3; ++a) sdir[a] *= 0.5 / len;
+    if (len <= 1e-15) break;
+    const int full = pd && len < 1e-4;
+    if (full && len >= prev_len) break;
+    prev_len = len;
+    const double slope = dot3(g, sdir);
+    double u[3], v[3];
+    frame_of(n, u, v);
+    int accepted = 0;
+    double lam = 1.0;
+    for (int bt = 0; bt < 60; ++bt, lam *= 0.5) {
+      double nt[3], Lt[10];
+      for (int a = 0; a < 3; ++a) nt[a] = n[a] + lam * (sdir[0] * u[a] + sdir[1] * v[a]);
+      double nn = sqrt(dot3(nt, nt));
+      for (int a = 0; a < 3; ++a) nt[a] /= nn;
+      const double tt = *tau + lam * sdir[2];
+      levin_terms(d, use, m, nt, tt, Lt);
+      if (full || Lt[0] <= L[0] + 1e-4 * lam * slope) {
+        for (int a = 0; a < 3; ++a) n[a] = nt[a];
+        *tau = tt;
+        for (int a = 0; a < 10; ++a) L[a] = Lt[a];
+        accepted = 1;
+        break;
+      }
+    }
+    if (!accepted) break;
+    if (fabs(*tau) > tmax) return 0;
+  }
+  return fabs(*tau) <= tmax;
+}
 
 /* O4 + O5 with the weights centred at r + h * tau * c (tau = 0: at r):
  * weighted moments about r in units of h, mu, C and the eigenpairs;
@@ -301,34 +480,56 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
     return ORC_PT_OUTLIER;
   }
 
-  /* O4, O5: the plane for the weights at r */
-  double nrm[3], lam[3], mu[3];
-  const double zero3[3] = {0.0, 0.0, 0.0};
-  double S0 = plane_fit(P, r, nb, k, h, 0.0, zero3, rad2, cs->ball, nrm, lam, mu);
-  /* O5b: weights moved to the current plane's projection of r */
-  for (int it = 0; it < cs->plane_iters; ++it) {
-    double c[3] = {nrm[0], nrm[1], nrm[2]};
-    S0 = plane_fit(P, r, nb, k, h, dot3(nrm, mu), c, rad2, cs->ball, nrm, lam, mu);
-  }
+  double nrm[3], lam[3], t, S0;
   uint8_t flags = 0;
   if (cs->ball && msup == k) flags |= ORC_PT_FLAG_TRUNCATED;
-  if (lam[1] - lam[0] < cs->ambig_gap * lam[2]) flags |= ORC_PT_FLAG_AMBIGUOUS;
-
-  /* O6 */
-  double t = dot3(nrm, mu);
+  if (cs->levin) {
+    /* O5c: from the plane of O4-O6 (weights at r) ... */
+    double mu[3];
+    const double zero3[3] = {0.0, 0.0, 0.0};
+    S0 = plane_fit(P, r, nb, k, h, 0.0, zero3, rad2, cs->ball, nrm, lam, mu);
+    if (lam[1] - lam[0] < cs->ambig_gap * lam[2]) flags |= ORC_PT_FLAG_AMBIGUOUS;
+    t = dot3(nrm, mu);
+    /* ... down to the local minimum of F, the list entries in units of h
+     * (those inside the ball, O3b) */
+    double *d = (double *)malloc(sizeof(double) * 3 * (size_t)k);
+    unsigned char *use = (unsigned char *)malloc((size_t)k);
+    int found = 0;
+    if (d && use) {
+      for (int j = 0; j < k; ++j) {
+        const double *p = P + 3 * (int64_t)nb[j];
+        for (int a = 0; a < 3; ++a) d[3 * j + a] = (p[a] - r[a]) / h;
+        use[j] = !(cs->ball && key3(p, r) > rad2);
+      }
+      found = levin_plane(d, use, k, cs->support_radius_h, nrm, &t);
+    }
+    free(d);
+    free(use);
+    if (!found) {
+      out[0] = r[0];
+      out[1] = r[1];
+      out[2] = r[2];
+      return ORC_PT_NO_MINIMUM | flags;
+    }
+  } else {
+    /* O4, O5: the plane for the weights at r */
+    double mu[3];
+    const double zero3[3] = {0.0, 0.0, 0.0};
+    S0 = plane_fit(P, r, nb, k, h, 0.0, zero3, rad2, cs->ball, nrm, lam, mu);
+    /* O5b: weights moved to the current plane's projection of r */
+    for (int it = 0; it < cs->plane_iters; ++it) {
+      double c[3] = {nrm[0], nrm[1], nrm[2]};
+      S0 = plane_fit(P, r, nb, k, h, dot3(nrm, mu), c, rad2, cs->ball, nrm, lam, mu);
+    }
+    if (lam[1] - lam[0] < cs->ambig_gap * lam[2]) flags |= ORC_PT_FLAG_AMBIGUOUS;
+    /* O6 */
+    t = dot3(nrm, mu);
+  }
   double q[3] = {r[0] + h * t * nrm[0], r[1] + h * t * nrm[1], r[2] + h * t * nrm[2]};
 
   /* O7 */
-  int ax = 0;
-  for (int a = 1; a < 3; ++a)
-    if (fabs(nrm[a]) < fabs(nrm[ax])) ax = a;
-  double ea[3] = {0, 0, 0};
-  ea[ax] = 1.0;
   double u[3], v[3];
-  cross3(ea, nrm, u);
-  double un = sqrt(dot3(u, u));
-  for (int a = 0; a < 3; ++a) u[a] /= un;
-  cross3(nrm, u, v);
+  frame_of(nrm, u, v);
 
   if (dg) {
     for (int a = 0; a < 3; ++a) {
@@ -424,7 +625,7 @@ static uint8_t project_one(const double *P, const double *r, const int32_t *nb,
 }
 
 static void fill_consts(orc_consts *cs, double support_radius_h, int min_support,
-                        int plane_iters, int ball) {
+                        int plane_iters, int ball, int levin) {
   cs->support_radius_h = support_radius_h;
   cs->min_support = min_support;
   cs->min_support_fit = 6;
@@ -432,18 +633,20 @@ static void fill_consts(orc_consts *cs, double support_radius_h, int min_support
   cs->ambig_gap = 1e-6;
   cs->plane_iters = plane_iters;
   cs->ball = ball;
+  cs->levin = levin;
 }
 
 /* Exported projection with given neighbour lists (m x k original indices). */
 int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
                 int32_t k, double h, const int32_t *nbr,
                 double support_radius_h, int32_t min_support, int32_t plane_iters,
-                int32_t ball, double *out, uint8_t *status, double *diag,
+                int32_t ball, int32_t levin, double *out, uint8_t *status, double *diag,
                 double *geo) {
   (void)n;
   if (k <= 0 || !(h > 0.0) || !isfinite(h) || plane_iters < 0) return 1;
+  if (levin && plane_iters) return 1;
   orc_consts cs;
-  fill_consts(&cs, support_radius_h, min_support, plane_iters, ball != 0);
+  fill_consts(&cs, support_radius_h, min_support, plane_iters, ball != 0, levin != 0);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t j = 0; j < m; ++j) {
     status[j] = project_one(P, Q + 3 * j, nbr + j * k, k, h, &cs, out + 3 * j,
@@ -463,7 +666,7 @@ int orc_grad_fd(const double *P, int64_t n, const double *Q, int64_t m,
                 double *gq, double *gp) {
   if (k <= 0 || !(h > 0.0)) return 1;
   orc_consts cs;
-  fill_consts(&cs, support_radius_h, min_support, 0, 0);
+  fill_consts(&cs, support_radius_h, min_support, 0, 0, 0);
   memset(gp, 0, sizeof(double) * 3 * (size_t)n);
   double step = rel_step * h;
   int nthr_fail = 0;
