@@ -27,7 +27,8 @@
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers unless marked (host). The caller
  *     owns every array and every workspace; the library allocates no device
- *     memory of its own.
+ *     memory of its own (its one device array of fixed size is the scratch
+ *     of mls_project_noalloc, in its code object).
  *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
  *     Calls are stream-ordered. mls_build_grid synchronises `stream` twice
  *     (to size the grid); the other calls never block the host.
@@ -294,6 +295,36 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
                                 uint8_t *out_status, int32_t *out_neighbors,
                                 void *out_normals, void *out_curvatures, void *workspace,
                                 size_t workspace_bytes, void *stream);
+
+/* ---- projection without allocation -------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one whole mls_project pass (params->stages MLS_STAGE_ALL, or
+ * MLS_STAGE_SEARCH | MLS_STAGE_FIT) whose projection workspace is a fixed
+ * device array inside the library, MLS_NOALLOC_SCRATCH_BYTES per GPU, which
+ * each GPU the call runs on holds until the process ends. The call
+ * allocates nothing; it takes the array's device address once per device
+ * (on its first call there, for the current device, which must be the
+ * device of `stream`). Inputs and outputs are the caller's, exactly as for
+ * mls_project, with the same results; the grid is built as usual.
+ *   Limit: the workspace mls_project_workspace_bytes(grid, params->k +
+ *   params->search_extra, n_queries) must fit the array (about 166 bytes per
+ *   query at k = 32: some 400,000 queries); larger calls return
+ *   MLS_ERR_WORKSPACE_TOO_SMALL before anything is launched, with the sizes
+ *   in mls_last_error().
+ *   Nothing in the array needs to start at zero: every call writes what it
+ *   reads. All calls on one GPU share its array, so calls on one GPU whose
+ *   work can overlap (different streams or threads without ordering between
+ *   them) race and give undefined results; order them on one stream.
+ *   The fit-only and refresh stages and the adjoint's reused lists cannot
+ *   continue from this call (MLS_ERR_INVALID_ARGUMENT for other stages).
+ * Errors: those of mls_project, and MLS_ERR_UNSUPPORTED for a device number
+ * of 64 or more. */
+#define MLS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mls_status mls_project_noalloc(const mls_grid *grid, const mls_params *params,
+                               const void *queries, mls_dtype dtype, int64_t n_queries,
+                               const int64_t *query_offsets, void *out_points,
+                               uint8_t *out_status, int32_t *out_neighbors, void *stream);
 
 /* Bytes of device workspace mls_project_backward needs: the projection's
  * workspace plus a sorted-order accumulation buffer of 3 values per cloud

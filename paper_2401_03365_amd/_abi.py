@@ -15,6 +15,7 @@ MLS_OK, MLS_ERR_INVALID_ARGUMENT, MLS_ERR_TOO_FEW_POINTS = 0, 1, 2
 MLS_ERR_UNSUPPORTED, MLS_ERR_WORKSPACE_TOO_SMALL, MLS_ERR_OUT_OF_MEMORY, MLS_ERR_HIP = 3, 4, 5, 6
 MLS_F32, MLS_F64 = 0, 1
 MLS_MAX_K = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MLS_MAX_PLANE_ITERS = 16
 MLS_PREC_FP64, MLS_PREC_FP32_MOMENTS = 0, 1
 MLS_STAGE_ALL, MLS_STAGE_SEARCH, MLS_STAGE_FIT, MLS_STAGE_REFRESH = 0, 1, 2, 4
@@ -64,6 +65,8 @@ SIGNATURES = {
                                    _P, _P, _P, _SZ, _P]),
     "mls_project_geometry": (_ST, [_P, ctypes.POINTER(MlsParams), _P, _ST, _I64, _P, _P, _P, _P,
                                    _P, _P, _P, _SZ, _P]),
+    "mls_project_noalloc": (_ST, [_P, ctypes.POINTER(MlsParams), _P, _ST, _I64, _P, _P, _P, _P,
+                                  _P]),
 }
 
 _lib = None

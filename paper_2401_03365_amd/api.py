@@ -206,6 +206,29 @@ class Grid:
             res = (out, status)
         return res + (nbr,) if return_neighbors else res
 
+    def project_noalloc(self, queries: torch.Tensor, k: int, precision: str = "fp32",
+                        query_offsets=None, out: Optional[torch.Tensor] = None,
+                        status: Optional[torch.Tensor] = None,
+                        neighbors: Optional[torch.Tensor] = None,
+                        support_radius_h: float = 3.0, min_support: int = 3):
+        """One whole projection pass through mls_project_noalloc: the
+        library's fixed device scratch replaces the workspace, so the call
+        allocates nothing when ``out``, ``status`` (and ``neighbors``, (n, k)
+        int32, if wanted) are given. Returns (out, status)."""
+        _check_points(queries, "queries", (torch.float32, torch.float64))
+        n = queries.shape[0]
+        params = self._params(k, precision, support_radius_h, min_support)
+        if out is None:
+            out = torch.empty_like(queries)
+        if status is None:
+            status = torch.empty((n,), dtype=torch.uint8, device=self.device)
+        qo, qo_p = _host_i64(query_offsets)
+        code = _abi.load().mls_project_noalloc(self._handle, ctypes.byref(params), _ptr(queries),
+                                               _dtype_code(queries), n, qo_p, _ptr(out),
+                                               _ptr(status), _ptr(neighbors), _stream())
+        _abi.check(code, "mls_project_noalloc")
+        return out, status
+
     def project_backward(self, queries: torch.Tensor, grad_out: torch.Tensor, k: int,
                          precision: str = "fp32", neighbors: Optional[torch.Tensor] = None,
                          query_offsets=None, support_radius_h: float = 3.0, min_support: int = 3,

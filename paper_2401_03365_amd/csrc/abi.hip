@@ -231,6 +231,44 @@ mls_status require_search(const void *ws, const mls_grid *grid, int32_t k, int32
   return MLS_ERR_INVALID_ARGUMENT;
 }
 
+// ---- the fixed scratch of mls_project_noalloc ------------------------------
+// The projection workspace of callers that cannot allocate: a device array of
+// fixed size in this library's code object. Every GPU holds its own copy, at
+// its own address, from the first use until the process ends. In host code
+// the array's name is not a device address: host code uses only the address
+// hipGetSymbolAddress returns on each device (taken once per device, with
+// that device current).
+constexpr size_t kScratchBytes = MLS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices];
+
+mls_status scratch_of_current_device(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    snprintf(g_last_error, sizeof g_last_error, "mls_project_noalloc: device %d not supported",
+             dev);
+    return MLS_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p & 255) != 0) {
+      snprintf(g_last_error, sizeof g_last_error, "mls_project_noalloc: bad scratch address");
+      return MLS_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MLS_OK;
+}
+
 }  // namespace
 
 struct mls_grid {
@@ -681,6 +719,41 @@ mls_status mls_project(const mls_grid *grid, const mls_params *params, const voi
   return mls_project_geometry(grid, params, queries, dtype, n_queries, query_offsets, out_points,
                               out_status, out_neighbors, nullptr, nullptr, workspace,
                               workspace_bytes, stream);
+}
+
+mls_status mls_project_noalloc(const mls_grid *grid, const mls_params *params,
+                               const void *queries, mls_dtype dtype, int64_t n_queries,
+                               const int64_t *query_offsets, void *out_points,
+                               uint8_t *out_status, int32_t *out_neighbors, void *stream) {
+  g_last_error[0] = 0;
+  if (!grid || !params) return MLS_ERR_INVALID_ARGUMENT;
+  if (!(params->stages == MLS_STAGE_ALL ||
+        params->stages == (MLS_STAGE_SEARCH | MLS_STAGE_FIT))) {
+    snprintf(g_last_error, sizeof g_last_error,
+             "mls_project_noalloc: only a whole pass (search and fit) is supported");
+    return MLS_ERR_INVALID_ARGUMENT;
+  }
+  const int32_t k_list = params->k + params->search_extra;
+  if (params->k < 1 || params->search_extra < 0 || k_list > MLS_MAX_K || n_queries < 0 ||
+      n_queries > 0x7fffffffll)
+    return MLS_ERR_INVALID_ARGUMENT;
+  const size_t need = proj_layout(grid->g.n_clouds, k_list, n_queries).total;
+  if (need > kScratchBytes) {
+    snprintf(g_last_error, sizeof g_last_error,
+             "mls_project_noalloc: %lld queries with %d list entries need %zu bytes of "
+             "scratch, above the fixed %zu",
+             (long long)n_queries, (int)k_list, need, kScratchBytes);
+    return MLS_ERR_WORKSPACE_TOO_SMALL;
+  }
+  void *ws = nullptr;
+  mls_status st = scratch_of_current_device(&ws);
+  if (st != MLS_OK) return st;
+  st = mls_project_geometry(grid, params, queries, dtype, n_queries, query_offsets, out_points,
+                            out_status, out_neighbors, nullptr, nullptr, ws, kScratchBytes,
+                            stream);
+  // the scratch is private to this call: no later stage may continue from it
+  forget_workspace(ws, kScratchBytes);
+  return st;
 }
 
 mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
