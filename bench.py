@@ -128,6 +128,8 @@ def parse():
     ap.add_argument("--plane-iters", type=int, default=3,
                     help="steps of the self-consistent reference plane in the extra "
                          "'plane_steps' measurement (0 skips it)")
+    ap.add_argument("--no-levin", action="store_true",
+                    help="skip the 'levin' measurement (Levin's reference plane per fit)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MB (3 times) and "
                          "print its bandwidth: the reference for the HBM traffic counters")
@@ -169,10 +171,10 @@ class Timer:
 
 
 def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer,
-              plane_iters=0):
+              plane_iters=0, levin=False):
     """Returns (ms_per_step, last outputs of pass 1, last final outputs).
-    ``plane_iters``: steps of the self-consistent reference plane in every
-    fit."""
+    ``plane_iters``: frozen-weight steps of the reference plane in every
+    fit; ``levin``: Levin's reference plane in every fit."""
     q0 = pts.double()
     first = None
     out = None
@@ -196,7 +198,7 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
                              search_extra=extra, refresh=refresh)
             with ctx("fit"):
                 grid.project(cur, k, precision, stages=2, out=nxt, status=status,
-                             search_extra=extra, plane_iters=plane_iters)
+                             search_extra=extra, plane_iters=plane_iters, levin=levin)
             if p == 0:
                 first = nxt
             cur = nxt
@@ -595,6 +597,21 @@ def main():
                              "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": ach / FP32_PEAK_TFLOPS, "traffic": None}}
 
+    first_lv = {}
+    if not args.no_levin:
+        # the same step with Levin's reference plane (Newton on Eq. (1.1)
+        # over (n, t), FP64 terms) in every fit, on both precision paths
+        res["levin"] = {}
+        for prec in ("fp32", "fp64"):
+            timer_lv = Timer(torch)
+            ms_lv, first_lv[prec], _ = run_steps(api, torch, pts, h, args.k, args.passes, prec,
+                                                 cell, max(1, args.steps // 2), 1, timer_lv,
+                                                 levin=True)
+            br_lv = {n: timer_lv.ms(n) for n in ("build", "search", "refresh", "fit")}
+            log("levin %s: %.2f ms/step  fit %.2f ms" % (prec, ms_lv, br_lv["fit"]))
+            res["levin"][prec] = {"value": args.n * args.passes / (ms_lv / 1000.0),
+                                  "unit": "pts/s", "ms_per_step": ms_lv, "breakdown_ms": br_lv}
+
     if not args.no_geometry:
         res["geometry"] = geometry_and_upsampling(api, torch, pts, h, cell, args.k)
         log("geometry: fit %.2f ms, with normals and curvatures %.2f ms; upsampling 4x: %.1f ms "
@@ -666,6 +683,16 @@ def main():
             res["plane_steps"]["accuracy_pass1_vs_oracle"] = {
                 "rms_over_h": float(np.sqrt((e ** 2).mean())), "max_over_h": float(e.max()),
                 "n": int(ok_ps.sum())}
+
+        for prec, fl in first_lv.items():
+            if fl is None:
+                continue
+            ref_lv, ref_lv_st = oracle.project(P64, Q, args.k, h, nbr=nbr, levin=True)
+            ok_lv = (ref_lv_st & 0x10) == 0
+            e = np.linalg.norm(fl.cpu().numpy()[sample] - ref_lv, axis=1)[ok_lv] / h
+            res["levin"][prec]["accuracy_pass1_vs_oracle"] = {
+                "rms_over_h": float(np.sqrt((e ** 2).mean())), "max_over_h": float(e.max()),
+                "n": int(ok_lv.sum())}
 
     print(json.dumps(res), flush=True)
 

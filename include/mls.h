@@ -77,6 +77,9 @@ enum {
   MLS_PT_PLANE_ONLY = 2, /* quadratic fit singular (support < 6 or a
                             Cholesky pivot <= 1e-12 * max diagonal); out = q */
   MLS_PT_NONFINITE = 3,  /* query has a NaN/Inf coordinate; out = NaN */
+  MLS_PT_NO_MINIMUM = 4, /* levin = 1: the descent to Levin's plane left the
+                            support radius (no local minimum of Eq. (1.1)
+                            within reach); out = r */
   MLS_PT_FLAG_NORMAL_AMBIGUOUS = 0x10, /* lambda2 - lambda1 < 1e-6 lambda3 */
   MLS_PT_FLAG_TRUNCATED = 0x20         /* ball neighbourhood: every one of the
                                           k list entries lies within the
@@ -116,6 +119,18 @@ typedef struct {
                                within R, else the status carries
                                MLS_PT_FLAG_TRUNCATED. Forward only, like
                                plane_iters. */
+  int32_t levin;            /* 0: the reference plane of plane_iters; 1:
+                               Levin's reference plane (Section 1.4): the
+                               local minimum over the unit normal n and the
+                               offset t of Eq. (1.1) with the weights at the
+                               plane's own projection q = r + t n, reached by
+                               Newton's method from the plane with the
+                               weights at r (that start plane and the descent
+                               in FP64 on both precision paths); a
+                               descent that leaves |t| <= support_radius_h * h
+                               gives MLS_PT_NO_MINIMUM. Excludes plane_iters
+                               (MLS_ERR_INVALID_ARGUMENT); forward only
+                               (the adjoint returns MLS_ERR_UNSUPPORTED). */
 } mls_params;
 
 /* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and

@@ -20,6 +20,7 @@ MLS_MAX_PLANE_ITERS = 16
 MLS_PREC_FP64, MLS_PREC_FP32_MOMENTS = 0, 1
 MLS_STAGE_ALL, MLS_STAGE_SEARCH, MLS_STAGE_FIT, MLS_STAGE_REFRESH = 0, 1, 2, 4
 PT_OK, PT_OUTLIER, PT_PLANE_ONLY, PT_NONFINITE, PT_FLAG_AMBIGUOUS = 0, 1, 2, 3, 0x10
+PT_NO_MINIMUM = 4
 PT_FLAG_TRUNCATED = 0x20
 MAX_K = 64
 
@@ -33,7 +34,8 @@ class MlsParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("support_radius_h", ctypes.c_double), ("min_support", ctypes.c_int32),
                 ("stages", ctypes.c_int32), ("search_extra", ctypes.c_int32),
-                ("plane_iters", ctypes.c_int32), ("ball", ctypes.c_int32)]
+                ("plane_iters", ctypes.c_int32), ("ball", ctypes.c_int32),
+                ("levin", ctypes.c_int32)]
 
 
 class MlsGridInfo(ctypes.Structure):

@@ -147,21 +147,21 @@ class Grid:
         return (nbr, keys) if return_keys else nbr
 
     def _params(self, k, precision, support_radius_h, min_support, stages=0, search_extra=0,
-                plane_iters=0, ball=False):
+                plane_iters=0, ball=False, levin=False):
         if precision not in PRECISIONS:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
                               support_radius_h=float(support_radius_h),
                               min_support=int(min_support), stages=int(stages),
                               search_extra=int(search_extra), plane_iters=int(plane_iters),
-                              ball=int(bool(ball)))
+                              ball=int(bool(ball)), levin=int(bool(levin)))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
                 support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
                 status: Optional[torch.Tensor] = None, search_extra: int = 0,
                 refresh: bool = False, plane_iters: int = 0, ball: bool = False,
-                geometry: bool = False):
+                geometry: bool = False, levin: bool = False):
         """One MLS projection pass. Returns (out, status[, neighbours]).
         ``stages``: 0 = search and fit, 1 = search only (lists stay in the
         grid's workspace), 2 = fit only from the preceding search.
@@ -170,6 +170,9 @@ class Grid:
         of the same queries' slots (exact; see MLS_STAGE_REFRESH);
         ``plane_iters``: steps of the reference plane with the weights at
         the plane's own projection of the query (0: weights at the query);
+        ``levin``: Levin's reference plane, the local minimum of Eq. (1.1)
+        over (n, t) with the weights at q = r + t n (status 4, NO_MINIMUM,
+        where the descent leaves the support radius);
         ``ball``: the neighbourhood is the list entries within
         support_radius_h * h (the paper's radius R), status flag 0x20 where
         the whole list lies inside it; ``geometry``: also return the surface
@@ -180,7 +183,7 @@ class Grid:
         if refresh:
             stages = (stages or (_abi.MLS_STAGE_SEARCH | _abi.MLS_STAGE_FIT)) | _abi.MLS_STAGE_REFRESH
         params = self._params(k, precision, support_radius_h, min_support, stages, search_extra,
-                              plane_iters, ball)
+                              plane_iters, ball, levin)
         if out is None:
             out = torch.empty_like(queries)
         if status is None:

@@ -660,7 +660,8 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
       params->min_support < 0 || params->stages < 0 || params->stages > 7 ||
       params->search_extra < 0 || params->search_extra > MLS_MAX_K ||
       params->plane_iters < 0 || params->plane_iters > MLS_MAX_PLANE_ITERS ||
-      (params->ball != 0 && params->ball != 1))
+      (params->ball != 0 && params->ball != 1) || (params->levin != 0 && params->levin != 1) ||
+      (params->levin && params->plane_iters))
     return MLS_ERR_INVALID_ARGUMENT;
   const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
   if ((stages & MLS_STAGE_REFRESH) && !(stages & MLS_STAGE_SEARCH))
@@ -707,7 +708,7 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
   if (stages & MLS_STAGE_FIT)
     MLS_HIP(mls::launch_mls_forward(grid->g.view, qv, params->k, params->precision,
                                     params->min_support, params->plane_iters, params->ball,
-                                    params->support_radius_h, nbr, support, out_points,
+                                    params->levin, params->support_radius_h, nbr, support, out_points,
                                     out_status, out_normals, out_curvatures, s));
   return MLS_OK;
 }
@@ -768,7 +769,8 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
       params->min_support < 0 || params->search_extra < 0 || params->search_extra > MLS_MAX_K)
     return MLS_ERR_INVALID_ARGUMENT;
-  if (params->plane_iters != 0 || params->ball != 0) return MLS_ERR_UNSUPPORTED;
+  if (params->plane_iters != 0 || params->ball != 0 || params->levin != 0)
+    return MLS_ERR_UNSUPPORTED;
   const int32_t k_list = params->k + params->search_extra;
   // stages: ALL = lists from `neighbors` or a fresh search; FIT = the lists a
   // preceding search left in this workspace

@@ -8,6 +8,10 @@
 //           with plane_iters > 0, that many more planes from the moments with
 //           the weights centred at the current q (Section 1.4: the weights
 //           of Eq. (1.1) belong to the projection of r onto the plane)
+//           or, with levin = 1, Levin's plane: the local minimum of Eq. (1.1)
+//           over (n, t) with the weights at q = r + t n, by Newton's method
+//           from this plane (mls_levin.h); none within the support radius
+//           -> status NO_MINIMUM, out = r
 // With ball = 1 every sum runs over the list entries whose canonical key to r
 // is at most (support_radius_h h)^2 (the paper's radius-R neighbourhood); a
 // list wholly inside that radius is flagged TRUNCATED.
@@ -31,6 +35,7 @@
 // into a compensated (hi, lo) FP32 pair with TwoSum; the eigen-solve and the
 // Cholesky stay FP64 in both.
 #include "mls_fit.h"
+#include "mls_levin.h"
 
 namespace mls {
 namespace {
@@ -58,7 +63,8 @@ __device__ __forceinline__ void store_geometry(void *normals, void *curv, int is
 template <bool kF32, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv, int32_t k,
                                                         int32_t min_support, int32_t plane_iters,
-                                                        int32_t ball, double support_radius_h,
+                                                        int32_t ball, int32_t levin,
+                                                        double support_radius_h,
                                                         void *__restrict__ out_normals,
                                                         void *__restrict__ out_curv,
                                                         const int32_t *__restrict__ nbr,
@@ -114,9 +120,30 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
       }
       if (m >= k) extra_flags = MLS_PT_FLAG_TRUNCATED;
     }
-    pass1_moments<kF32, false, true>(g, nb, k, rel, S0, S1, S2, nullptr, 0.0, nullptr, nullptr,
-                                     mask);
+    if (kF32 && levin) {
+      // the start of the descent decides which local minimum it reaches, so
+      // the FP32-moment path starts it from the FP64 plane as well
+      const Rel<false> rel64(r, 1.0 / h);
+      pass1_moments<false, false, true>(g, nb, k, rel64, S0, S1, S2, nullptr, 0.0, nullptr,
+                                        nullptr, mask);
+    } else {
+      pass1_moments<kF32, false, true>(g, nb, k, rel, S0, S1, S2, nullptr, 0.0, nullptr,
+                                       nullptr, mask);
+    }
     pf = plane_from_moments(S0, S1, S2, r, h);
+    if (levin) {
+      double n[3] = {pf.n[0], pf.n[1], pf.n[2]};
+      double tau = pf.t;
+      if (!levin_descend(g, nb, k, r, 1.0 / h, support_radius_h, mask, n, tau)) {
+        store_vec(out, qv.is_f64, qi, r);
+        status[qi] = MLS_PT_NO_MINIMUM | pf.flags | extra_flags;
+        const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+        const double o[3] = {nanv, nanv, nanv};
+        store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+        return;
+      }
+      pf = plane_of(n, tau, r, h, pf.flags);
+    }
     for (int it = 0; it < plane_iters; ++it) {
       const Real<kF32> tn[3] = {(Real<kF32>)(pf.t * pf.n[0]), (Real<kF32>)(pf.t * pf.n[1]),
                                 (Real<kF32>)(pf.t * pf.n[2])};
@@ -167,28 +194,30 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
 
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               int32_t precision, int32_t min_support, int32_t plane_iters,
-                              int32_t ball, double support_radius_h, const int32_t *nbr,
-                              const uint8_t *support, void *out, uint8_t *status,
-                              void *out_normals, void *out_curvatures, hipStream_t s) {
+                              int32_t ball, int32_t levin, double support_radius_h,
+                              const int32_t *nbr, const uint8_t *support, void *out,
+                              uint8_t *status, void *out_normals, void *out_curvatures,
+                              hipStream_t s) {
   if (qv.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((qv.n + kBlock - 1) / kBlock);
   const bool f32 = precision == MLS_PREC_FP32_MOMENTS;
-  const bool ext = plane_iters != 0 || ball != 0 || out_normals || out_curvatures;
+  const bool ext = plane_iters != 0 || ball != 0 || levin != 0 || out_normals ||
+                   out_curvatures;
   if (f32 && !ext)
     hipLaunchKernelGGL((k_mls_forward<true, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, 0, 0, support_radius_h, nullptr, nullptr, nbr, support, out,
+                       min_support, 0, 0, 0, support_radius_h, nullptr, nullptr, nbr, support, out,
                        status);
   else if (f32)
     hipLaunchKernelGGL((k_mls_forward<true, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv, k,
-                       min_support, plane_iters, ball, support_radius_h, out_normals,
+                       min_support, plane_iters, ball, levin, support_radius_h, out_normals,
                        out_curvatures, nbr, support, out, status);
   else if (!ext)
     hipLaunchKernelGGL((k_mls_forward<false, false>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
-                       k, min_support, 0, 0, support_radius_h, nullptr, nullptr, nbr, support,
+                       k, min_support, 0, 0, 0, support_radius_h, nullptr, nullptr, nbr, support,
                        out, status);
   else
     hipLaunchKernelGGL((k_mls_forward<false, true>), dim3(blocks), dim3(kBlock), 0, s, g, qv,
-                       k, min_support, plane_iters, ball, support_radius_h, out_normals,
+                       k, min_support, plane_iters, ball, levin, support_radius_h, out_normals,
                        out_curvatures, nbr, support, out, status);
   return hipGetLastError();
 }

@@ -199,7 +199,8 @@ hipError_t launch_knn(const GridView &g, const QueryView &qv, int32_t k, int32_t
                       hipStream_t s);
 hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               int32_t precision, int32_t min_support, int32_t plane_iters,
-                              int32_t ball, double support_radius_h, const int32_t *nbr_tiles,
+                              int32_t ball, int32_t levin, double support_radius_h,
+                              const int32_t *nbr_tiles,
                               const uint8_t *support, void *out, uint8_t *status,
                               void *out_normals, void *out_curvatures, hipStream_t s);
 hipError_t launch_lists_from_caller(const GridView &g, const QueryView &qv, int32_t k,

@@ -7,7 +7,8 @@ brute-force kNN over the whole cloud:
   height field 10,000,000, k = 48, 3 iterated passes, FP32-moment and FP64
       paths (each pass checked against the oracle fed the GPU's own pass
       input), one pass
-      with 3 steps of the self-consistent reference plane, and 40,000,000
+      with 3 frozen-weight steps of the reference plane, one pass with
+      Levin's plane (both paths), and 40,000,000
       upsampling queries (positions, lists, geometry);
   bumped sphere 2,000,000, k = 32, FP32 forward and the adjoint (1,000
       queries against central finite differences);
@@ -126,6 +127,27 @@ def test_heightfield_10m_plane_steps(orc):
     ref_nbr, _ = orc.knn(P64, Qs, 48)
     check_projection(orc, P64, Qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
                      "fp32", nbr=ref_nbr, plane_iters=3, label="plane steps")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_heightfield_10m_levin(orc, precision):
+    # Levin's reference plane (Newton on Eq. (1.1) over (n, t)), one call
+    # over the whole cloud as timed
+    print("10M height field, Levin plane, %s" % precision, flush=True)
+    P = synth.heightfield(10_000_000, sigma=1e-3, seed=3)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h, cell_size=1.25 * h)
+    rng = np.random.default_rng(26)
+    idx = np.sort(rng.choice(P.shape[0], 256, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    out, st = g.project(Pt.double(), 48, precision, levin=True)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    Qs = P64[idx]
+    ref_nbr, _ = orc.knn(P64, Qs, 48)
+    check_projection(orc, P64, Qs, 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(),
+                     precision, nbr=ref_nbr, levin=True, label="levin 10M")
 
 
 def test_heightfield_10m_upsampling_40m(orc):
