@@ -86,6 +86,30 @@ def search_traffic_bytes(args):
     return kib * 1024.0
 
 
+FIT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fit_heightfield10M_k48.json")
+FIT_SOURCES = [os.path.join(ROOT, "paper_2401_03365_amd", "csrc", f)
+               for f in ("mls_fwd.hip", "mls_fit.h", "mls_math.h", "mls_levin.h")]
+
+
+def fit_traffic_bytes(args):
+    """HBM bytes per fit launch from the recorded counter runs, or None when
+    the fit's sources changed since they were taken or the workload differs."""
+    import hashlib
+    try:
+        with open(FIT_TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    hsh = hashlib.sha256()
+    for fn in FIT_SOURCES:
+        with open(fn, "rb") as fh:
+            hsh.update(fh.read())
+    if rec.get("source_sha256") != hsh.hexdigest() or rec.get("n") != args.n or \
+            rec.get("k") != args.k:
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def search_valu_busy(args):
     """Fraction of the VALU issue capacity the full searches use, from the
     recorded SQ_INSTS_VALU counter runs, or None when the kernel's source
@@ -115,7 +139,7 @@ def parse():
     ap.add_argument("--passes", type=int, default=3)
     ap.add_argument("--cell-factor", type=float, default=None,
                     help="cell edge in units of h (default: library tuning table)")
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=12288)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
@@ -128,6 +152,10 @@ def parse():
     ap.add_argument("--plane-iters", type=int, default=3,
                     help="steps of the self-consistent reference plane in the extra "
                          "'plane_steps' measurement (0 skips it)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the sphere 20k and torus 1.01M one-pass measurements")
+    ap.add_argument("--acc-sample", type=int, default=2048,
+                    help="queries per workload and pass in the accuracy table")
     ap.add_argument("--no-levin", action="store_true",
                     help="skip the 'levin' measurement (Levin's reference plane per fit)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -172,22 +200,25 @@ class Timer:
 
 def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer,
               plane_iters=0, levin=False):
-    """Returns (ms_per_step, last outputs of pass 1, last final outputs).
+    """Returns (ms_per_step, last outputs of pass 1, last final outputs,
+    [(input, output, status) of every pass of the last step]).
     ``plane_iters``: frozen-weight steps of the reference plane in every
     fit; ``levin``: Levin's reference plane in every fit."""
     q0 = pts.double()
     first = None
     out = None
+    passes_io = []
 
     def step(record):
-        nonlocal first, out
+        nonlocal first, out, passes_io
+        passes_io = []
         ctx = timer.span if record else (lambda name: _Null())
         with ctx("build"):
             grid = api.Grid(pts, h, cell_size=cell)
         cur = q0
-        status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
         for p in range(passes):
             nxt = torch.empty_like(cur)
+            status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
             # the pass before the first refreshed one keeps SEARCH_EXTRA more
             # neighbours; refreshed passes re-rank the lists of the pass
             # before (exact; a fresh search where not certified)
@@ -201,6 +232,7 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
                              search_extra=extra, plane_iters=plane_iters, levin=levin)
             if p == 0:
                 first = nxt
+            passes_io.append((cur, nxt, status))
             cur = nxt
         out = cur
         return grid
@@ -214,7 +246,7 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
         step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0) * 1000.0 / steps, first, out
+    return (t1 - t0) * 1000.0 / steps, first, out, passes_io
 
 
 class _Null:
@@ -225,11 +257,13 @@ class _Null:
         return False
 
 
-def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label):
+def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label, precision="fp32",
+            keep=None):
     """fwd (search + fit) and the adjoint of one pass over the whole cloud,
-    queries = the cloud's points, FP32-moment path, FP32 in and out. The grid
-    is built once; the loss gradient is torch code between the two and is
-    timed apart. value = N / (t_fwd + t_bwd)."""
+    queries = the cloud's points (FP32 in and out), on the FP32-moment or the
+    FP64 path. The grid is built once; the loss gradient is torch code between
+    the two and is timed apart. value = N / (t_fwd + t_bwd). ``keep``: a dict
+    that receives the forward's outputs and statuses."""
     pts = torch.from_numpy(P).cuda()
     timer = Timer(torch)
     grid = api.Grid(pts, h, cell_size=default_cell_factor(k) * h)
@@ -239,13 +273,13 @@ def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label):
     def step(record):
         ctx = timer.span if record else (lambda name: _Null())
         with ctx("fwd_search"):
-            grid.project(pts, k, "fp32", stages=1, out=out, status=status)
+            grid.project(pts, k, precision, stages=1, out=out, status=status)
         with ctx("fwd_fit"):
-            grid.project(pts, k, "fp32", stages=2, out=out, status=status)
+            grid.project(pts, k, precision, stages=2, out=out, status=status)
         with ctx("loss_grad"):
             gy = loss_grad(out)
         with ctx("bwd"):
-            gq, gp = grid.project_backward(pts, gy, k, "fp32", reuse_lists=True)
+            gq, gp = grid.project_backward(pts, gy, k, precision, reuse_lists=True)
         return gq, gp
 
     for _ in range(warmup):
@@ -257,11 +291,14 @@ def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label):
     br = {n: timer.ms(n) for n in ("fwd_search", "fwd_fit", "loss_grad", "bwd")}
     t = br["fwd_search"] + br["fwd_fit"] + br["bwd"]
     ok = bool(torch.isfinite(gq).all().item() and torch.isfinite(gp).all().item())
-    log("%s: fwd %.2f + %.2f ms, loss %.2f ms, bwd %.2f ms, finite grads %s" %
-        (label, br["fwd_search"], br["fwd_fit"], br["loss_grad"], br["bwd"], ok))
+    log("%s %s: fwd %.2f + %.2f ms, loss %.2f ms, bwd %.2f ms, finite grads %s" %
+        (label, precision, br["fwd_search"], br["fwd_fit"], br["loss_grad"], br["bwd"], ok))
+    if keep is not None:
+        keep["out"], keep["status"] = out, status
     del grid
     return {"value": P.shape[0] / (t / 1000.0), "unit": "pts/s", "n_points": int(P.shape[0]),
-            "k": k, "h": h, "breakdown_ms": br, "ms_fwd_plus_bwd": t, "grads_finite": ok}
+            "k": k, "h": h, "precision": precision, "breakdown_ms": br, "ms_fwd_plus_bwd": t,
+            "grads_finite": ok}
 
 
 def sh_sphere_loss(torch, field, P):
@@ -342,7 +379,7 @@ def batch_loss_grad(torch, P, off, shapes, n_total):
     return grad
 
 
-def batch_fwd_bwd(api, torch, steps, warmup):
+def batch_fwd_bwd(api, torch, steps, warmup, keep=None):
     """256 clouds (~30M points, sizes log-normal, sphere / torus / height
     field, per-cloud h), k = 32, FP32: the cell edge is tuned, the grid built
     once, then [search, fit, loss gradient, adjoint] is captured in one HIP
@@ -406,6 +443,8 @@ def batch_fwd_bwd(api, torch, steps, warmup):
         float((gp_g - gp_e).norm() / gp_e.norm()) <= 1e-5
     log("batch: graph %.2f ms/step, eager %.2f ms/step, build %.2f ms, finite grads %s" %
         (graph_ms, eager_ms, build_ms, ok))
+    if keep is not None:
+        keep.update({"P": P, "off": off, "h": h, "out": out, "status": status})
     return {"value": P.shape[0] / (graph_ms / 1000.0), "unit": "pts/s",
             "n_points": int(P.shape[0]), "n_clouds": int(len(h)), "k": k,
             "ms_per_step_graph": graph_ms, "ms_per_step_eager": eager_ms, "build_ms": build_ms,
@@ -451,6 +490,127 @@ def geometry_and_upsampling(api, torch, pts, h, cell, k, reps=3):
             "upsample_4x": {"n_queries": int(up.shape[0]), "ms": up_ms,
                             "value": up.shape[0] / (up_ms / 1000.0), "unit": "pts/s",
                             "step": "search + fit of 4 jittered queries per sample"}}
+
+
+def one_pass(api, torch, P, h, k, precision, reps=5, cell_factor=1.25):
+    """One projection pass (search + fit) of the cloud's own points, grid
+    built once; mean ms over ``reps`` after a warm-up. Returns (result dict,
+    outputs, statuses)."""
+    pts = torch.from_numpy(P).cuda()
+    g = api.Grid(pts, h, cell_size=cell_factor * h)
+    q = pts.double()
+    out = torch.empty_like(q)
+    st = torch.empty((pts.shape[0],), dtype=torch.uint8, device="cuda")
+    g.project(q, k, precision, out=out, status=st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.project(q, k, precision, out=out, status=st)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    g.close()
+    return ({"precision": precision, "ms_per_pass": ms,
+             "value": P.shape[0] / (ms / 1000.0), "unit": "pts/s"}, out, st)
+
+
+def small_configs(api, torch, keep):
+    """The sphere (20k, k = 32, FP64 path; FP32 beside it) and the torus
+    with outliers (1.01M, k = 32, both paths): one pass each."""
+    from paper_2401_03365_amd import synth
+    res = {}
+    P1 = synth.sphere(20000, 0.01, seed=1)
+    h1 = synth.mean_nn_h(P1)
+    P2 = synth.torus(1_000_000, sigma=0.005, n_outliers=10_000, seed=2)
+    h2 = synth.mean_nn_h(P2)
+    for name, P, hh in (("sphere_20k_k32", P1, h1), ("torus_1.01M_k32", P2, h2)):
+        res[name] = {"n_points": int(P.shape[0]), "h": hh}
+        for prec in ("fp64", "fp32"):
+            r, out, st = one_pass(api, torch, P, hh, 32, prec)
+            res[name][prec] = r
+            keep[(name, prec)] = (P, hh, 32, out, st)
+            log("%s %s: %.3f ms per pass (%.3g pts/s)" % (name, prec, r["ms_per_pass"], r["value"]))
+    return res
+
+
+def accuracy_of(oracle, P, Q, k, h, out, st, **kw):
+    """max and RMS |GPU - oracle| / h over the sampled queries Q (rows of
+    out/st), lists by the oracle's brute force; points flagged ambiguous and
+    non-finite queries left out of the error, status mismatches counted."""
+    P64 = P.astype(np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    nbr, _ = oracle.knn(P64, Q, k)
+    ref, ref_st = oracle.project(P64, Q, k, h, nbr=nbr, **kw)[:2]
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) != 3)
+    out = np.asarray(out)
+    diff = np.abs(out.astype(np.float64) - ref)
+    if out.dtype == np.float32:
+        # outputs stored in FP32: their storage rounding (an ulp per
+        # coordinate) is not an error of the arithmetic
+        diff = np.maximum(diff - np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64), 0)
+    e = np.linalg.norm(diff, axis=1)[ok] / h
+    return {"rms_over_h": float(np.sqrt((e ** 2).mean())) if e.size else 0.0,
+            "max_over_h": float(e.max()) if e.size else 0.0, "n": int(ok.sum()),
+            "status_mismatches": int((np.asarray(st) != ref_st).sum()),
+            "outputs": "fp32 (storage rounding allowed)" if out.dtype == np.float32 else "fp64"}
+
+
+def sample_rows(torch, n, m, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n, size=min(m, n), replace=False))
+    return idx, torch.from_numpy(idx).cuda()
+
+
+def cpu_info():
+    """Model, sockets, threads per core and the cores this process may use."""
+    info = {"cores_available": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            key = key.strip()
+            if key in ("Socket(s)", "Thread(s) per core", "Core(s) per socket", "CPU(s)"):
+                info[key] = val.strip()
+    except Exception:
+        pass
+    return info
+
+
+def adjoint_check(api, torch, oracle, P, h, m=1000, k=32):
+    """The adjoint on m sampled queries of the cloud (lists from the oracle's
+    brute force, passed in) against the oracle's central differences:
+    relative 2-norm errors of the query and the point gradients."""
+    P64 = P.astype(np.float64)
+    rng = np.random.default_rng(23)
+    idx = np.sort(rng.choice(P.shape[0], m, replace=False))
+    Qs = P64[idx]
+    nbr, _ = oracle.knn(P64, Qs, k)
+    _, st = oracle.project(P64, Qs, k, h, nbr=nbr)
+    keepq = (st & 0x10) == 0
+    Qs, nbr = Qs[keepq], nbr[keepq]
+    go = rng.normal(size=Qs.shape)
+    fq, fp = oracle.grad_fd(P64, Qs, k, h, nbr, go)
+    g = api.Grid(torch.from_numpy(P).cuda(), h, cell_size=1.25 * h)
+    res = {"n_queries": int(Qs.shape[0])}
+    for prec in ("fp32", "fp64"):
+        gq, gp = g.project_backward(torch.from_numpy(Qs).cuda(), torch.from_numpy(go).cuda(), k,
+                                    prec, neighbors=torch.from_numpy(nbr).cuda())
+        torch.cuda.synchronize()
+        gq, gp = gq.cpu().numpy(), gp.cpu().numpy()
+        res[prec] = {"query_grad_rel": float(np.linalg.norm(gq - fq) / np.linalg.norm(fq)),
+                     "point_grad_rel": float(np.linalg.norm(gp - fp) / np.linalg.norm(fp))}
+    g.close()
+    return res
 
 
 def quality_table(api, torch):
@@ -522,8 +682,8 @@ def main():
     torch.cuda.synchronize()
 
     timer = Timer(torch)
-    ms32, first32, out32 = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", cell,
-                                     args.steps, args.warmup, timer)
+    ms32, first32, out32, io32 = run_steps(api, torch, pts, h, args.k, args.passes, "fp32",
+                                           cell, args.steps, args.warmup, timer)
     br32 = {n: timer.ms(n) for n in ("build", "search", "refresh", "fit")}
     log("fp32: %.2f ms/step  build %.2f  search %.2f  refresh %.2f  fit %.2f (ms per call)" %
         (ms32, br32["build"], br32["search"], br32["refresh"], br32["fit"]))
@@ -531,10 +691,11 @@ def main():
 
     fp64 = None
     first64 = None
+    io64 = None
     if not args.no_fp64:
         timer64 = Timer(torch)
-        ms64, first64, _ = run_steps(api, torch, pts, h, args.k, args.passes, "fp64", cell,
-                                     max(1, args.steps // 2), 1, timer64)
+        ms64, first64, _, io64 = run_steps(api, torch, pts, h, args.k, args.passes, "fp64",
+                                           cell, max(1, args.steps // 2), 1, timer64)
         br64 = {n: timer64.ms(n) for n in ("build", "search", "refresh", "fit")}
         log("fp64: %.2f ms/step  build %.2f  search %.2f  refresh %.2f  fit %.2f" %
             (ms64, br64["build"], br64["search"], br64["refresh"], br64["fit"]))
@@ -562,6 +723,13 @@ def main():
         # pipes' issue cycles it fills (counters), beside the flop fraction
         roof["valu_issue_busy"] = search_valu_busy(args)
 
+    # the fit of the headline step: ALU-bound (FP32 moments, FP64 solves)
+    flops_fit = nq * (args.k * FIT_FLOPS_PER_NEIGHBOUR + FIT_FP64_FLOPS_PER_QUERY)
+    ach_fit = flops_fit / (br32["fit"] / 1000.0) / 1e12
+    fit_roof = {"kernel": "k_mls_forward<fp32>", "bound": "alu", "achieved": ach_fit,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach_fit / FP32_PEAK_TFLOPS,
+                "traffic": fit_traffic_bytes(args)}
+
     res = {"metric": METRIC, "value": value, "unit": "pts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms32, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -573,16 +741,17 @@ def main():
            "value_excl_build": args.n * args.passes /
            ((ms32 - br32["build"]) / 1000.0),
            "fp64_path": fp64,
-           "roofline": roof}
+           "roofline": roof,
+           "fit_roofline": fit_roof}
 
     first_ps = None
     if args.plane_iters > 0:
         # the same step with the reference plane's weights moved to its own
         # projection of the query (Section 1.4), plane_iters steps per fit
         timer_ps = Timer(torch)
-        ms_ps, first_ps, _ = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", cell,
-                                       max(1, args.steps // 2), 1, timer_ps,
-                                       plane_iters=args.plane_iters)
+        ms_ps, first_ps, _, _ = run_steps(api, torch, pts, h, args.k, args.passes, "fp32",
+                                          cell, max(1, args.steps // 2), 1, timer_ps,
+                                          plane_iters=args.plane_iters)
         br_ps = {n: timer_ps.ms(n) for n in ("build", "search", "refresh", "fit")}
         log("plane steps %d: %.2f ms/step  fit %.2f ms" % (args.plane_iters, ms_ps, br_ps["fit"]))
         # fit with steps: pass 1 once plus once per step, pass 2 once
@@ -604,9 +773,9 @@ def main():
         res["levin"] = {}
         for prec in ("fp32", "fp64"):
             timer_lv = Timer(torch)
-            ms_lv, first_lv[prec], _ = run_steps(api, torch, pts, h, args.k, args.passes, prec,
-                                                 cell, max(1, args.steps // 2), 1, timer_lv,
-                                                 levin=True)
+            ms_lv, first_lv[prec], _, _ = run_steps(api, torch, pts, h, args.k, args.passes,
+                                                    prec, cell, max(1, args.steps // 2), 1,
+                                                    timer_lv, levin=True)
             br_lv = {n: timer_lv.ms(n) for n in ("build", "search", "refresh", "fit")}
             log("levin %s: %.2f ms/step  fit %.2f ms" % (prec, ms_lv, br_lv["fit"]))
             res["levin"][prec] = {"value": args.n * args.passes / (ms_lv / 1000.0),
@@ -631,20 +800,35 @@ def main():
             ({s_: (r["R"], round(r["mean"], 5), r["input_mean"]) for s_, r in best.items()},
              time.perf_counter() - t))
 
+    keep = {}
+    if not args.no_small:
+        res["small_configs"] = small_configs(api, torch, keep)
+
     if not args.no_fwd_bwd:
         fb = {}
-        fb["heightfield_10M_k48"] = fwd_bwd(api, torch, P, h, args.k,
-                                            heightfield_loss(torch, hfield),
-                                            args.steps, args.warmup, "fwd+bwd heightfield")
+        for prec in ("fp32", "fp64"):
+            key = "heightfield_10M_k48" + ("" if prec == "fp32" else "_fp64")
+            fb[key] = fwd_bwd(api, torch, P, h, args.k, heightfield_loss(torch, hfield),
+                              args.steps, args.warmup, "fwd+bwd heightfield", precision=prec)
         P4, shf = synth.sh_sphere(args.c4_n, sigma=0.005, seed=4, return_field=True)
         h4 = synth.mean_nn_h(P4)
-        fb["sh_sphere_2M_k32"] = fwd_bwd(api, torch, P4, h4, 32, sh_sphere_loss(torch, shf, P4),
-                                         args.steps, args.warmup, "fwd+bwd sh sphere")
+        for prec in ("fp32", "fp64"):
+            key = "sh_sphere_2M_k32" + ("" if prec == "fp32" else "_fp64")
+            kk = {}
+            fb[key] = fwd_bwd(api, torch, P4, h4, 32, sh_sphere_loss(torch, shf, P4),
+                              args.steps, args.warmup, "fwd+bwd sh sphere", precision=prec,
+                              keep=kk)
+            keep[("sh_sphere_2M_k32", prec)] = (P4, h4, 32, kk["out"], kk["status"])
         if not args.no_batch:
-            fb["batch_256_clouds_30M_k32"] = batch_fwd_bwd(api, torch, args.steps, args.warmup)
+            kb = {}
+            fb["batch_256_clouds_30M_k32"] = batch_fwd_bwd(api, torch, args.steps, args.warmup,
+                                                           keep=kb)
+            keep["batch"] = kb
         res["fwd_bwd"] = fb
 
     if not args.no_cpu_baseline:
+        # the CPU leg: the oracle timed on the host's cores, and the GPU's
+        # accuracy against it on every workload
         import oracle
         rng = np.random.default_rng(7)
         sample = np.sort(rng.choice(args.n, size=min(args.cpu_sample, args.n), replace=False))
@@ -654,16 +838,35 @@ def main():
         nbr, _ = oracle.knn(P64, Q, args.k)
         ref, ref_st = oracle.project(P64, Q, args.k, h, nbr=nbr)
         dt = time.perf_counter() - t
+        # the fit alone on 1M queries, lists from SciPy's k-d tree (any lists
+        # serve for timing); the brute-force search's cost per query; the k-d
+        # tree's own k-nearest rate as a third-party CPU reference
+        from scipy.spatial import cKDTree
+        ci = cpu_info()
+        threads = int(os.environ.get("OMP_NUM_THREADS", ci["cores_available"]))
+        tree = cKDTree(P64, balanced_tree=False, compact_nodes=False)
+        m_fit = min(1_000_000, args.n)
+        Qf = P64[:m_fit]
+        t3 = time.perf_counter()
+        _, nb_f = tree.query(Qf, args.k, workers=threads)
+        dt_tree = time.perf_counter() - t3
+        nb_f = nb_f.astype(np.int32)
         t2 = time.perf_counter()
-        oracle.project(P64, Q, args.k, h, nbr=nbr)
+        oracle.project(P64, Qf, args.k, h, nbr=nb_f)
         dt_fit = time.perf_counter() - t2
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        res["cpu_baseline"] = {"value": len(sample) / dt, "unit": "pts/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": "%d random queries of pass 1 of the same 10M cloud "
-                                         "(brute-force kNN over all points + FP64 projection)"
-                                         % len(sample),
-                               "fit_only_pts_s": len(sample) / dt_fit}
+        del nb_f, tree
+        res["cpu_baseline"] = {
+            "value": len(sample) / dt, "unit": "pts/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random queries of pass 1 of the same 10M cloud (brute-force kNN "
+                      "over all points + FP64 projection)" % len(sample),
+            "cpu": ci,
+            "fit_only_pts_s": m_fit / dt_fit,
+            "fit_only_sample": "the first %d points of the cloud as queries, lists of %d from "
+                               "SciPy cKDTree" % (m_fit, args.k),
+            "brute_force_knn_s_per_query": dt / len(sample),
+            "ckdtree_knn_pts_s": m_fit / dt_tree}
+        log("cpu oracle %.0f pts/s (brute force + fit), fit alone %.3g pts/s, cKDTree %.3g pts/s "
+            "on %d threads, %s" % (len(sample) / dt, m_fit / dt_fit, m_fit / dt_tree, threads, ci))
         ok = (ref_st & 0x10) == 0
         acc = {}
         for name, first in (("fp32", first32), ("fp64", first64)):
@@ -674,7 +877,57 @@ def main():
             acc[name] = {"rms_over_h": float(np.sqrt((e ** 2).mean())), "max_over_h": float(e.max()),
                          "n": int(ok.sum())}
         res["accuracy_pass1_vs_oracle"] = acc
-        log("cpu oracle %.0f pts/s on %d cores; accuracy %s" % (len(sample) / dt, cores, acc))
+
+        # accuracy per workload, path and pass (sampled queries, the oracle's
+        # brute-force lists)
+        t = time.perf_counter()
+        table = {}
+        m = args.acc_sample
+        for prec, io in (("fp32", io32), ("fp64", io64)):
+            if io is None:
+                continue
+            for p_i, (qin, qout, qst) in enumerate(io):
+                idx, idx_t = sample_rows(torch, args.n, m, 100 + p_i)
+                table["heightfield_10M_k48/pass%d/%s" % (p_i + 1, prec)] = accuracy_of(
+                    oracle, P, qin[idx_t].cpu().numpy(), args.k, h,
+                    qout[idx_t].cpu().numpy(), qst[idx_t].cpu().numpy())
+        for key, val in keep.items():
+            if key == "batch":
+                continue
+            name, prec = key
+            Pc, hc, kc, outc, stc = val
+            idx, idx_t = sample_rows(torch, Pc.shape[0], m, 200)
+            table["%s/%s" % (name, prec)] = accuracy_of(
+                oracle, Pc, Pc[idx], kc, hc, outc[idx_t].cpu().numpy(), stc[idx_t].cpu().numpy())
+        if "batch" in keep:
+            kb = keep["batch"]
+            off, hb = kb["off"], kb["h"]
+            out_b, st_b = kb["out"].cpu().numpy(), kb["status"].cpu().numpy()
+            e_all, n_all, mism = [], 0, 0
+            per = max(1, m // (len(off) - 1))
+            for c in range(len(off) - 1):
+                Pc = kb["P"][off[c]:off[c + 1]]
+                rng_c = np.random.default_rng(300 + c)
+                li = np.sort(rng_c.choice(Pc.shape[0], size=min(per, Pc.shape[0]), replace=False))
+                a_c = accuracy_of(oracle, Pc, Pc[li], 32, hb[c], out_b[off[c] + li],
+                                  st_b[off[c] + li])
+                e_all.append((a_c["rms_over_h"] ** 2 * a_c["n"], a_c["max_over_h"]))
+                n_all += a_c["n"]
+                mism += a_c["status_mismatches"]
+            table["batch_256_clouds_30M_k32/fp32"] = {
+                "rms_over_h": float(np.sqrt(sum(x for x, _ in e_all) / max(n_all, 1))),
+                "max_over_h": float(max(y for _, y in e_all)), "n": n_all,
+                "status_mismatches": mism}
+        res["accuracy_vs_oracle"] = table
+        log("accuracy table (%.1f s): %s" % (time.perf_counter() - t, json.dumps(table)))
+
+        # the adjoint against the oracle's central differences on 1,000
+        # queries of the bumped sphere, both paths
+        if ("sh_sphere_2M_k32", "fp32") in keep:
+            P4c, h4c = keep[("sh_sphere_2M_k32", "fp32")][:2]
+            res["adjoint_vs_fd"] = adjoint_check(api, torch, oracle, P4c, h4c)
+            log("adjoint vs central differences: %s" % res["adjoint_vs_fd"])
+
         if first_ps is not None:
             ref_ps, ref_ps_st = oracle.project(P64, Q, args.k, h, nbr=nbr,
                                                plane_iters=args.plane_iters)
