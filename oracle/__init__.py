@@ -31,7 +31,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mls_oracle.c")
-_LIB = os.path.join(_HERE, "libmls_oracle.so")
+# MLS_ORACLE_SANITIZE=1 builds and loads an AddressSanitizer +
+# UndefinedBehaviorSanitizer build instead (the Python process must preload
+# the sanitizer runtimes)
+_SANITIZE = os.environ.get("MLS_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libmls_oracle_san.so" if _SANITIZE else "libmls_oracle.so")
 
 PT_OK, PT_OUTLIER, PT_PLANE_ONLY, PT_NONFINITE, PT_NO_MINIMUM = 0, 1, 2, 3, 4
 PT_FLAG_AMBIGUOUS = 0x10
@@ -51,6 +55,9 @@ def build(force: bool = False) -> str:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
                "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC, "-lm"]
+        if _SANITIZE:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                        "-fno-omit-frame-pointer", "-g"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
