@@ -17,6 +17,8 @@ NumPy arrays. Every function follows the paper's MLS projection:
                    smallest-|t| local minimum over (n, t)), local frame, weighted
                    quadratic height fit and projection (Section 2.1,
                    Algorithm 1), outlier rule (Section 3.3).
+* ``project_ball`` -- the same steps over the radius-R ball without a count
+                   cap (brute force over the cloud, Section 1.4 / Section 3.3).
 * ``grad_fd``   -- J^T g by central finite differences with lists fixed.
 
 Parity pins for each function are in ``tests/test_oracle_*.py``.
@@ -75,6 +77,8 @@ def _load():
         lib.orc_project.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, i32, i32, i32, P, P, P,
                                     P]
         lib.orc_project.restype = ctypes.c_int
+        lib.orc_project_ball.argtypes = [P, i64, P, i64, f64, f64, i32, i32, i32, P, P, P, P, P]
+        lib.orc_project_ball.restype = ctypes.c_int
         lib.orc_grad_fd.argtypes = [P, i64, P, i64, i32, f64, P, f64, i32, P, f64, P, P]
         lib.orc_grad_fd.restype = ctypes.c_int
         lib.orc_diag_stride.restype = ctypes.c_int
@@ -139,6 +143,28 @@ def project(P, Q, k, h, nbr=None, support_radius_h=3.0, min_support=3, diag=Fals
         raise ValueError("orc_project failed (%d)" % rc)
     res = (out, st) + ((dg,) if diag else ()) + ((geo,) if geometry else ())
     return res
+
+
+def project_ball(P, Q, h, support_radius_h=3.0, min_support=3, diag=False, geometry=False,
+                 plane_iters=0, levin=False):
+    """One projection pass over the paper's radius-R neighbourhood without a
+    count cap (O3c): every cloud point within R = support_radius_h * h of the
+    query (canonical keys, brute force). Returns (out, status, counts
+    [, diag] [, geometry])."""
+    lib = _load()
+    P, Q = _c64(P), _c64(Q)
+    m = Q.shape[0]
+    out = np.empty((m, 3), dtype=np.float64)
+    st = np.empty(m, dtype=np.uint8)
+    cnt = np.empty(m, dtype=np.int64)
+    dg = np.empty((m, lib.orc_diag_stride()), dtype=np.float64) if diag else None
+    geo = np.empty((m, 5), dtype=np.float64) if geometry else None
+    rc = lib.orc_project_ball(_ptr(P), P.shape[0], _ptr(Q), m, float(h), float(support_radius_h),
+                              int(min_support), int(plane_iters), int(bool(levin)), _ptr(out),
+                              _ptr(st), _ptr(dg), _ptr(geo), _ptr(cnt))
+    if rc:
+        raise ValueError("orc_project_ball failed (%d)" % rc)
+    return (out, st, cnt) + ((dg,) if diag else ()) + ((geo,) if geometry else ())
 
 
 def grad_fd(P, Q, k, h, nbr, gout, rel_step=1e-6, support_radius_h=3.0, min_support=3):

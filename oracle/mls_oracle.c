@@ -55,6 +55,10 @@
  *       the k nearest, so the ball is complete when fewer than k entries lie
  *       within R; when all k do, the ball may hold more points than the list
  *       and the query is flagged TRUNCATED (its k nearest are used).
+ *   O3c (orc_project_ball) the paper's neighbourhood of radius R without a
+ *       count cap: every cloud point whose O1 key to r is at most R^2, R =
+ *       support_radius_h * h, found by brute force (in index order); that
+ *       list then takes the steps O3-O10 (its support m is its size).
  *   O6  plane H through r + h*mu with normal n; its origin q is the orthogonal
  *       projection of r onto H: q = r + h <n, mu> n (Section 2.1: the
  *       projection of the point onto H defines the origin q).
@@ -653,6 +657,75 @@ int orc_project(const double *P, int64_t n, const double *Q, int64_t m,
                             diag ? diag + ORC_DIAG * j : NULL, geo ? geo + 5 * j : NULL);
   }
   return 0;
+}
+
+/* O3c: the ball of radius R = support_radius_h * h around every query, by
+ * brute force over the cloud, then O3-O10 over it (plane_iters and levin as
+ * in orc_project). counts[j] receives the ball's size. */
+int orc_project_ball(const double *P, int64_t n, const double *Q, int64_t m, double h,
+                     double support_radius_h, int32_t min_support, int32_t plane_iters,
+                     int32_t levin, double *out, uint8_t *status, double *diag, double *geo,
+                     int64_t *counts) {
+  if (!(h > 0.0) || !isfinite(h) || plane_iters < 0 || !(support_radius_h > 0.0)) return 1;
+  if (levin && plane_iters) return 1;
+  orc_consts cs;
+  fill_consts(&cs, support_radius_h, min_support, plane_iters, 0, levin != 0);
+  const double rad = support_radius_h * h;
+  const double rad2 = rad * rad;
+  int fail = 0;
+#pragma omp parallel
+  {
+    int64_t cap = 256;
+    int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    if (!nb) {
+#pragma omp atomic write
+      fail = 1;
+    }
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t j = 0; j < m; ++j) {
+      if (!nb) continue;
+      const double *r = Q + 3 * j;
+      int64_t c = 0;
+      if (finite3(r)) {
+        for (int64_t i = 0; i < n; ++i) {
+          if (!finite3(P + 3 * i) || !(key3(P + 3 * i, r) <= rad2)) continue;
+          if (c == cap) {
+            int32_t *grown = (int32_t *)realloc(nb, sizeof(int32_t) * (size_t)(2 * cap));
+            if (!grown) {
+#pragma omp atomic write
+              fail = 1;
+              break;
+            }
+            nb = grown;
+            cap *= 2;
+          }
+          nb[c++] = (int32_t)i;
+        }
+      }
+      counts[j] = c;
+      if (c == 0) {
+        /* no point within R (or a non-finite query): O3 with an empty list */
+        double *o = out + 3 * j;
+        if (diag)
+          for (int t = 0; t < ORC_DIAG; ++t) diag[ORC_DIAG * j + t] = NAN;
+        if (geo)
+          for (int t = 0; t < 5; ++t) geo[5 * j + t] = NAN;
+        if (!finite3(r)) {
+          o[0] = o[1] = o[2] = NAN;
+          status[j] = ORC_PT_NONFINITE;
+        } else {
+          o[0] = r[0]; o[1] = r[1]; o[2] = r[2];
+          status[j] = ORC_PT_OUTLIER;
+          if (diag) diag[ORC_DIAG * j + 21] = 0.0;
+        }
+        continue;
+      }
+      status[j] = project_one(P, r, nb, (int)c, h, &cs, out + 3 * j,
+                              diag ? diag + ORC_DIAG * j : NULL, geo ? geo + 5 * j : NULL);
+    }
+    free(nb);
+  }
+  return fail ? 2 : 0;
 }
 
 /* O12: J^T g by central finite differences, lists and statuses fixed.
