@@ -117,8 +117,14 @@ typedef struct {
                                k-nearest list entries within R (canonical
                                keys): exact when fewer than k entries lie
                                within R, else the status carries
-                               MLS_PT_FLAG_TRUNCATED. Forward only, like
-                               plane_iters. */
+                               MLS_PT_FLAG_TRUNCATED; 2: the same
+                               neighbourhood without a count cap: every cloud
+                               point whose canonical key to the query is at
+                               most R^2, however many (k is unused; the call
+                               must run all stages and return no lists, the
+                               support count is the ball's size; plane_iters
+                               and levin return MLS_ERR_UNSUPPORTED). Forward
+                               only, like plane_iters. */
   int32_t levin;            /* 0: the reference plane of plane_iters; 1:
                                Levin's reference plane (Section 1.4): the
                                local minimum over the unit normal n and the

@@ -154,7 +154,7 @@ class Grid:
                               support_radius_h=float(support_radius_h),
                               min_support=int(min_support), stages=int(stages),
                               search_extra=int(search_extra), plane_iters=int(plane_iters),
-                              ball=int(bool(ball)), levin=int(bool(levin)))
+                              ball=int(ball), levin=int(bool(levin)))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
@@ -173,9 +173,10 @@ class Grid:
         ``levin``: Levin's reference plane, the local minimum of Eq. (1.1)
         over (n, t) with the weights at q = r + t n (status 4, NO_MINIMUM,
         where the descent leaves the support radius);
-        ``ball``: the neighbourhood is the list entries within
+        ``ball``: 1 (or True): the neighbourhood is the list entries within
         support_radius_h * h (the paper's radius R), status flag 0x20 where
-        the whole list lies inside it; ``geometry``: also return the surface
+        the whole list lies inside it; 2: every cloud point within that
+        radius, no count cap (k unused, no lists returned); ``geometry``: also return the surface
         normal (n, 3) and the mean and Gaussian curvature (n, 2) at each
         output, after the status: (out, status, normals, curvatures[, nbr])."""
         _check_points(queries, "queries", (torch.float32, torch.float64))

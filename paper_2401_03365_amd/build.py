@@ -18,7 +18,8 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libmls.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["abi.hip", "grid.hip", "knn.hip", "mls_fwd.hip", "mls_bwd.hip", "autotune.hip"]
+SOURCES = ["abi.hip", "grid.hip", "knn.hip", "mls_fwd.hip", "mls_bwd.hip", "ball.hip",
+           "autotune.hip"]
 PER_FILE_FLAGS = {"knn.hip": ["-ffp-contract=off"]}
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -660,7 +660,7 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
       params->min_support < 0 || params->stages < 0 || params->stages > 7 ||
       params->search_extra < 0 || params->search_extra > MLS_MAX_K ||
       params->plane_iters < 0 || params->plane_iters > MLS_MAX_PLANE_ITERS ||
-      (params->ball != 0 && params->ball != 1) || (params->levin != 0 && params->levin != 1) ||
+      params->ball < 0 || params->ball > 2 || (params->levin != 0 && params->levin != 1) ||
       (params->levin && params->plane_iters))
     return MLS_ERR_INVALID_ARGUMENT;
   const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
@@ -672,6 +672,24 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
   hipStream_t s = (hipStream_t)stream;
   mls::QueryView qv;
   ProjLayout L;
+  if (params->ball == 2) {
+    // the ball without a count cap: one kernel, no lists (k unused)
+    if (stages != (MLS_STAGE_SEARCH | MLS_STAGE_FIT) || out_neighbors) {
+      snprintf(g_last_error, sizeof g_last_error,
+               "ball = 2 projects in one call (all stages) and returns no lists");
+      return MLS_ERR_INVALID_ARGUMENT;
+    }
+    if (params->plane_iters || params->levin) return MLS_ERR_UNSUPPORTED;
+    if (workspace && n_queries > 0)
+      forget_workspace(workspace, proj_layout(grid->g.n_clouds, 1, n_queries).total);
+    mls_status st = prepare_queries(grid, 1, 1, queries, dtype, n_queries, query_offsets,
+                                    workspace, workspace_bytes, true, s, &qv, &L);
+    if (st != MLS_OK || n_queries == 0) return st;
+    MLS_HIP(mls::launch_ball(grid->g.view, qv, params->precision, params->min_support,
+                             params->support_radius_h, out_points, out_status, out_normals,
+                             out_curvatures, s));
+    return MLS_OK;
+  }
   const int32_t k_list = params->k + params->search_extra;
   // a fresh search sorts queries that are not the grid's points; refresh and
   // fit-only calls keep the slots of the preceding search, which must be the

@@ -203,6 +203,11 @@ hipError_t launch_mls_forward(const GridView &g, const QueryView &qv, int32_t k,
                               const int32_t *nbr_tiles,
                               const uint8_t *support, void *out, uint8_t *status,
                               void *out_normals, void *out_curvatures, hipStream_t s);
+// The projection over the radius-R ball without a count cap (one wave per
+// query; no lists).
+hipError_t launch_ball(const GridView &g, const QueryView &qv, int32_t precision,
+                       int32_t min_support, double support_radius_h, void *out, uint8_t *status,
+                       void *out_normals, void *out_curvatures, hipStream_t s);
 hipError_t launch_lists_from_caller(const GridView &g, const QueryView &qv, int32_t k,
                                     const int32_t *user, int32_t *nbr_tiles, hipStream_t s);
 hipError_t launch_mls_backward(const GridView &g, const QueryView &qv, int32_t k,

@@ -31,10 +31,14 @@ def api():
     return a
 
 
-def check(orc, P64, Q, k, h, out, st, precision, radius_h, iters=0):
-    ref_nbr, _ = orc.knn(P64, Q, k)
-    ref, ref_st, dg = orc.project(P64, Q, k, h, nbr=ref_nbr, ball=True,
-                                  support_radius_h=radius_h, plane_iters=iters, diag=True)
+def check(orc, P64, Q, k, h, out, st, precision, radius_h, iters=0, uncapped=False):
+    if uncapped:
+        # every cloud point within R (the oracle's brute-force ball)
+        ref, ref_st, _, dg = orc.project_ball(P64, Q, h, support_radius_h=radius_h, diag=True)
+    else:
+        ref_nbr, _ = orc.knn(P64, Q, k)
+        ref, ref_st, dg = orc.project(P64, Q, k, h, nbr=ref_nbr, ball=True,
+                                      support_radius_h=radius_h, plane_iters=iters, diag=True)
     piv = np.where(np.isfinite(dg[:, 23]), dg[:, 23], 1.0)
     # the FP32-moment path takes the pivot decision (OK or PLANE_ONLY) on its
     # own moments, whose relative rounding (~1e-7) does not resolve a pivot
@@ -139,3 +143,111 @@ def test_heightfield_10m_ball(orc):
     P64 = P.astype(np.float64)
     check(orc, P64, P64[idx], 48, h, out[idx_t].cpu().numpy(), st[idx_t].cpu().numpy(), "fp32",
           1.8)
+
+
+# ---- the ball without a count cap (ball = 2) ---------------------------------
+
+@pytest.mark.parametrize("radius_h", [1.5, 3.0, 6.0])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uncapped_ball_matches_oracle(orc, precision, radius_h):
+    print("uncapped ball: sphere 20000, R = %.1f h, %s" % (radius_h, precision), flush=True)
+    P = synth.sphere(20000, 0.01, seed=1)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h)
+    out, st = g.project(Pt.double(), 1, precision, ball=2, support_radius_h=radius_h)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    ref_st = check(orc, P64, P64, 1, h, out.cpu().numpy(), st.cpu().numpy(), precision, radius_h,
+                   uncapped=True)
+    assert not np.any(ref_st & 0x20)
+    if radius_h == 6.0:
+        _, _, cnt = orc.project_ball(P64, P64[:200], h, support_radius_h=radius_h)
+        assert cnt.min() > 64  # balls beyond any k-nearest list
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uncapped_ball_torus_outliers_offsets_and_fp32_queries(orc, precision):
+    # a batch of two clouds (torus with outliers, height field), FP32 queries
+    # that are not the points (query offsets), off-surface and non-finite ones
+    print("uncapped ball: batch, %s" % precision, flush=True)
+    A = synth.torus(12000, sigma=0.005, n_outliers=300, seed=58)
+    B = synth.heightfield(9000, sigma=1e-3, seed=59)
+    hA, hB = synth.mean_nn_h(A), synth.mean_nn_h(B)
+    P = np.concatenate([A, B]).astype(np.float32)
+    off = [0, A.shape[0], P.shape[0]]
+    rng = np.random.default_rng(60)
+    QA = (A[rng.choice(A.shape[0], 1500, replace=False)] +
+          rng.uniform(-0.5, 0.5, (1500, 3)).astype(np.float32) * np.float32(hA))
+    QB = (B[rng.choice(B.shape[0], 1000, replace=False)] +
+          rng.uniform(-0.5, 0.5, (1000, 3)).astype(np.float32) * np.float32(hB))
+    QA[3] = np.nan
+    Q = np.concatenate([QA, QB]).astype(np.float32)
+    g = api().Grid(torch.from_numpy(P).cuda(), [hA, hB], cloud_offsets=off)
+    out, st = g.project(torch.from_numpy(Q).cuda(), 1, precision, ball=2, support_radius_h=2.5,
+                        query_offsets=[0, 1500, 2500])
+    torch.cuda.synchronize()
+    out, st = out.cpu().numpy(), st.cpu().numpy()
+    for (lo, hi), Pc, hc in (((0, 1500), A, hA), ((1500, 2500), B, hB)):
+        check(orc, Pc.astype(np.float64), Q[lo:hi].astype(np.float64), 1, hc, out[lo:hi],
+              st[lo:hi], precision, 2.5, uncapped=True)
+    assert (st[3] & 0x0F) == 3
+    assert int(((st[:1500] & 0x0F) == 1).sum()) > 5  # some outliers
+
+
+def test_uncapped_ball_quadric_apex_on_larger_patches():
+    # the golden bowl and saddle patches grown to 81 points: the ball covers
+    # the whole symmetric patch and the FP64 path returns the apex exactly
+    from test_oracle_project import load_golden, quadric_case
+    for c in load_golden()["quadric_apex"]:
+        c = dict(c)
+        c["lattice_half"] = 4
+        P, Q = quadric_case(c)
+        Pt = torch.from_numpy(P.astype(np.float32)).cuda()
+        g = api().Grid(Pt, c["h"])
+        R = 2.0 * 4 * c["spacing"] * 1.5
+        out, st = g.project(torch.from_numpy(Q).cuda(), 1, "fp64", ball=2,
+                            support_radius_h=R / c["h"])
+        torch.cuda.synchronize()
+        assert (int(st[0]) & 0x0F) == 0
+        np.testing.assert_allclose(out.cpu().numpy()[0], c["expected"], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uncapped_ball_geometry(orc, precision):
+    P = synth.sphere(20000, 0.01, seed=62)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h)
+    out, st, nrm, curv = g.project(Pt.double(), 1, precision, ball=2, support_radius_h=3.0,
+                                   geometry=True)
+    torch.cuda.synchronize()
+    P64 = P.astype(np.float64)
+    _, ref_st, _, geo = orc.project_ball(P64, P64, h, support_radius_h=3.0, geometry=True)
+    ok = ((ref_st & 0x10) == 0) & ((ref_st & 0x0F) == 0) & ((st.cpu().numpy() & 0x0F) == 0)
+    N, G = nrm.cpu().numpy()[ok], geo[ok]
+    sgn = np.sign(np.sum(N * G[:, :3], axis=1))
+    dn = np.abs(N * sgn[:, None] - G[:, :3]).max()
+    dH = np.abs(curv.cpu().numpy()[ok, 0] * sgn - G[:, 3]).max() * h
+    if precision == "fp64":
+        assert dn <= 1e-9 and dH <= 1e-8, (dn, dH)
+    else:
+        assert dn <= 1e-3 and dH <= 1e-2, (dn, dH)
+
+
+def test_uncapped_ball_argument_rules():
+    from paper_2401_03365_amd import _abi
+    P = synth.sphere(3000, 0.01, seed=63)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h)
+    for kw, code in ((dict(return_neighbors=True), _abi.MLS_ERR_INVALID_ARGUMENT),
+                     (dict(stages=1), _abi.MLS_ERR_INVALID_ARGUMENT),
+                     (dict(levin=True), _abi.MLS_ERR_UNSUPPORTED),
+                     (dict(plane_iters=2), _abi.MLS_ERR_UNSUPPORTED)):
+        with pytest.raises(_abi.MLSError) as ei:
+            g.project(Pt, 16, "fp32", ball=2, **kw)
+        assert ei.value.code == code, kw
+    with pytest.raises(_abi.MLSError) as ei:
+        g.project(Pt, 16, "fp32", ball=3)
+    assert ei.value.code == _abi.MLS_ERR_INVALID_ARGUMENT
