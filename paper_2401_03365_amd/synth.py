@@ -44,6 +44,26 @@ def sphere(n, sigma=0.01, seed=1):
     return _f32((1.0 + sigma * z)[:, None] * nh)
 
 
+def cube(n, sigma=0.01, seed=1, half=0.5):
+    """Surface of the cube [-half, half]^3 (a shape with sharp edges and
+    corners), area-uniform (each of the 6 faces equally likely), noise sigma
+    along the face normal."""
+    rng = np.random.default_rng(seed)
+    face = rng.integers(0, 6, n)
+    axis, side = face // 2, np.where(face % 2 == 0, -1.0, 1.0)
+    P = rng.uniform(-half, half, (n, 3))
+    P[np.arange(n), axis] = side * (half + sigma * rng.standard_normal(n))
+    return _f32(P)
+
+
+def cube_distance(Y, half=0.5):
+    """Distance from each row of Y to the surface of the cube [-half, half]^3."""
+    q = np.abs(np.asarray(Y, dtype=np.float64)) - half
+    outside = np.linalg.norm(np.maximum(q, 0.0), axis=1)
+    inside = np.minimum(q.max(axis=1), 0.0)
+    return outside + np.abs(inside)
+
+
 def sphere_cap(n, cap_angle, seed=0, radius=1.0):
     """Noise-free samples of a spherical cap around +z (area-uniform)."""
     rng = np.random.default_rng(seed)

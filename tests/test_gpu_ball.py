@@ -235,6 +235,27 @@ def test_uncapped_ball_geometry(orc, precision):
         assert dn <= 1e-3 and dH <= 1e-2, (dn, dH)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uncapped_ball_cube_200k_sampled(orc, precision):
+    # the quality protocol's largest balls: the 200k cube at R = 0.05 (about
+    # 260 points per ball, edges and corners), every query on the GPU, 600
+    # sampled ones against the oracle's brute-force ball
+    print("uncapped ball: cube 200k, R = 0.05, %s" % precision, flush=True)
+    P = synth.cube(200_000, 0.01, seed=62)
+    R = 0.05
+    h = R / 3.0
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h)
+    out, st = g.project(Pt, 1, precision, ball=2, support_radius_h=3.0)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(64).choice(P.shape[0], 600, replace=False))
+    P64 = P.astype(np.float64)
+    check(orc, P64, P64[idx], 1, h, out.cpu().numpy()[idx], st.cpu().numpy()[idx], precision,
+          3.0, uncapped=True)
+    _, _, cnt = orc.project_ball(P64, P64[idx[:50]], h, support_radius_h=3.0)
+    assert np.median(cnt) > 150
+
+
 def test_uncapped_ball_argument_rules():
     from paper_2401_03365_amd import _abi
     P = synth.sphere(3000, 0.01, seed=63)
