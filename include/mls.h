@@ -215,6 +215,25 @@ mls_status mls_build_grid(const float *points, int64_t n_points,
                           void *workspace, size_t workspace_bytes, void *stream,
                           mls_grid **out_grid);
 
+/* Rebuilds a built grid for new positions of its points (the same count,
+ * clouds, h and cell sizes), without any host synchronisation, copy or
+ * memset: every step is a kernel on `stream`, so a caller can capture a
+ * rebuild in a HIP graph with the calls that use the grid (a training step
+ * that moves the cloud, then searches and projects it again).
+ *   points   n_points x 3 FP32 (device), the new positions.
+ * The rebuild keeps the first build's grid geometry (origin, cell edges,
+ * cells per axis) and table size: a point that moves out of the first
+ * build's box is assigned to the nearest edge cell, which keeps every search
+ * exact (a cell at the grid's edge is never behind a face the search
+ * certifies against). The cell table takes, on the device, the longest
+ * prefix of the first build's levels whose cells fill at most half of it; a
+ * level left out finds nothing, which the search treats as an empty block
+ * (exact, slower). Host-side facts (mls_get_grid_info: cell and non-finite
+ * counts) are those of the first build. Workspaces whose lists came from
+ * this grid can no longer serve MLS_STAGE_FIT, MLS_STAGE_REFRESH or reused
+ * adjoint lists. Errors: INVALID_ARGUMENT (null arguments), HIP. */
+mls_status mls_rebuild_grid(mls_grid *grid, const float *points, void *stream);
+
 /* Frees the host handle only (the workspace is the caller's). */
 mls_status mls_grid_destroy(mls_grid *grid);
 

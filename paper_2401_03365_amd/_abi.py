@@ -52,6 +52,7 @@ SIGNATURES = {
     "mls_grid_workspace_bytes": (_SZ, [_I64, _I32]),
     "mls_build_grid": (_ST, [_P, _I64, _P, _I32, _P, _P, _P, _SZ, _P, ctypes.POINTER(_P)]),
     "mls_grid_destroy": (_ST, [_P]),
+    "mls_rebuild_grid": (_ST, [_P, _P, _P]),
     "mls_get_grid_info": (_ST, [_P, ctypes.POINTER(MlsGridInfo)]),
     "mls_get_cloud_grid": (_ST, [_P, _I32, _P, _P, _P]),
     "mls_grid_sorted_points": (_ST, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),

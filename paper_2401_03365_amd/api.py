@@ -88,6 +88,17 @@ class Grid:
         self._proj_ws = None
         self._retired_ws = []
 
+    def rebuild(self, points: torch.Tensor):
+        """Re-sorts the grid for new positions of its points (same shape)
+        with kernels only, so it can sit in a captured HIP graph; the grid
+        keeps its first build's geometry (see mls_rebuild_grid)."""
+        _check_points(points, "points")
+        if points.shape[0] != self.n_points:
+            raise ValueError("rebuild needs the same number of points")
+        code = _abi.load().mls_rebuild_grid(self._handle, _ptr(points), _stream())
+        _abi.check(code, "mls_rebuild_grid")
+        self.points = points
+
     # ---- facts ------------------------------------------------------------
     def info(self) -> dict:
         info = _abi.MlsGridInfo()

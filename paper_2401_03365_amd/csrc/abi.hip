@@ -38,7 +38,7 @@ uint64_t next_pow2(uint64_t x) {
 // Byte layout of the grid workspace.
 struct GridLayout {
   size_t pts, inv_perm, keys_a, keys_b, vals_a, vals_b, radix, table, clouds, offsets, bbox,
-      nonfinite, counter, total;
+      nonfinite, counter, levels, total;
   uint64_t table_cap_max;
 };
 
@@ -60,6 +60,7 @@ GridLayout grid_layout(int64_t n, int32_t c) {
   L.bbox = take(24 * (size_t)c);
   L.nonfinite = take(8 * (size_t)c);
   L.counter = take(64);
+  L.levels = take(64);  // levels in the table after a rebuild (device)
   L.total = o;
   return L;
 }
@@ -461,6 +462,8 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   }
   const unsigned long long ncells = level_cells[0];
   STEP(mls::launch_build_table(skeys, n_points, n_levels, table, cap, s));
+  int32_t *levels_dev = (int32_t *)(ws + L.levels);
+  STEP(mls::launch_set_i32(levels_dev, n_levels, s));
 #undef STEP
 
   gh.view.pts = pts;
@@ -472,6 +475,7 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   gh.view.morton_bits = bits;
   gh.view.n_points = n_points;
   gh.view.n_levels = n_levels;
+  gh.view.levels = levels_dev;
   {
     int shift = 64;
     for (uint64_t c = cap; c > 1; c >>= 1) --shift;
@@ -490,6 +494,49 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   gh.workspace_bytes = workspace_bytes;
   *out_grid = G;
   return cleanup(MLS_OK);
+}
+
+mls_status mls_rebuild_grid(mls_grid *grid, const float *points, void *stream) {
+  g_last_error[0] = 0;
+  if (!grid || !points) return MLS_ERR_INVALID_ARGUMENT;
+  mls_status st = check_async();
+  if (st != MLS_OK) return st;
+  mls::GridHost &gh = grid->g;
+  const int64_t n = gh.n_points;
+  const int32_t C = gh.n_clouds;
+  const GridLayout L = grid_layout(n, C);
+  char *ws = (char *)gh.workspace;
+  float4 *pts = (float4 *)(ws + L.pts);
+  int32_t *inv_perm = (int32_t *)(ws + L.inv_perm);
+  uint64_t *keys_a = (uint64_t *)(ws + L.keys_a), *keys_b = (uint64_t *)(ws + L.keys_b);
+  int32_t *vals_a = (int32_t *)(ws + L.vals_a), *vals_b = (int32_t *)(ws + L.vals_b);
+  uint4 *table = (uint4 *)(ws + L.table);
+  mls::CloudDev *clouds = (mls::CloudDev *)(ws + L.clouds);
+  const int64_t *offsets_dev = (const int64_t *)(ws + L.offsets);
+  uint32_t *bbox = (uint32_t *)(ws + L.bbox);
+  unsigned long long *nonfin = (unsigned long long *)(ws + L.nonfinite);
+  unsigned long long *counter = (unsigned long long *)(ws + L.counter);
+  int32_t *levels = (int32_t *)(ws + L.levels);
+  int64_t max_cloud = 0;
+  for (int32_t c = 0; c < C; ++c) max_cloud = std::max(max_cloud, gh.offsets[c + 1] - gh.offsets[c]);
+  hipStream_t s = (hipStream_t)stream;
+  // lists that searches on this grid left in workspaces hold the old sorted
+  // positions: no later stage may continue from them
+  forget_grid(grid);
+  MLS_HIP(mls::launch_bbox(points, offsets_dev, C, max_cloud, bbox, nonfin, s));
+  MLS_HIP(mls::launch_cloud_ranges(clouds, C, nonfin, s));
+  MLS_HIP(mls::launch_keys(points, clouds, C, max_cloud, gh.view.morton_bits, keys_a, vals_a, s));
+  bool in_alt = false;
+  MLS_HIP(mls::radix_sort_pairs(keys_a, vals_a, keys_b, vals_b, n, gh.key_bits, ws + L.radix,
+                                &in_alt, s));
+  const uint64_t *skeys = in_alt ? keys_b : keys_a;
+  const int32_t *svals = in_alt ? vals_b : vals_a;
+  MLS_HIP(mls::launch_gather(points, svals, n, pts, inv_perm, s));
+  MLS_HIP(mls::launch_clear_u64(counter, mls::kMaxLevels, s));
+  MLS_HIP(mls::launch_count_cells(skeys, n, gh.view.n_levels, counter, s));
+  MLS_HIP(mls::launch_table_dev_levels(skeys, n, gh.view.n_levels, counter, levels, table,
+                                       (uint64_t)gh.hash_capacity, s));
+  return MLS_OK;
 }
 
 mls_status mls_grid_destroy(mls_grid *grid) {

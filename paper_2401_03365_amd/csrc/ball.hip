@@ -144,8 +144,9 @@ __global__ __launch_bounds__(64 * kBallWaves) void k_ball(GridView g, QueryView 
     // per axis (clamped to the grid)
     int lev = -1;
     int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    const int nlev = levels_of(g);
 #pragma clang loop vectorize(disable) interleave(disable)
-    for (int l = 0; l < g.n_levels && lev < 0 && cd.send > cd.sbegin; ++l) {
+    for (int l = 0; l < nlev && lev < 0 && cd.send > cd.sbegin; ++l) {
       const double icell = ldexp(cd.inv_cell, -l);
       bool fits = true;
 #pragma unroll

@@ -386,9 +386,125 @@ __global__ __launch_bounds__(kThreads) void k_table_insert(const uint64_t *__res
   }
 }
 
+// ---- rebuild ------------------------------------------------------------------------
+// A rebuild keeps the first build's geometry and table size; what depends on
+// the new points is decided on the device, so that no host round trip sits
+// between the steps.
+
+__global__ void k_set_i32(int32_t *p, int32_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_clear_u64(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Sorted ranges of the clouds' finite points (non-finite points sort last).
+__global__ void k_cloud_ranges(CloudDev *__restrict__ clouds, int32_t n_clouds,
+                               const unsigned long long *__restrict__ nonfinite) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t at = 0;
+  for (int32_t c = 0; c < n_clouds; ++c) {
+    const int64_t fin = (clouds[c].end - clouds[c].begin) - (int64_t)nonfinite[c];
+    clouds[c].sbegin = at;
+    clouds[c].send = at + (fin > 0 ? fin : 0);
+    at = clouds[c].send;
+  }
+}
+
+// The levels of the table: the longest prefix of levels whose cells fill at
+// most half of the capacity (a level left out is absent from the hash: its
+// lookups find nothing, which the search treats as an empty block and
+// widens, so results stay exact).
+__global__ void k_levels_fit(const unsigned long long *__restrict__ counts, int n_levels,
+                             uint64_t capacity, int32_t *__restrict__ levels_out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  uint64_t total = 0;
+  int fit = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    total += counts[l];
+    if (2 * total > capacity) break;
+    fit = l + 1;
+  }
+  *levels_out = fit;
+}
+
+__global__ __launch_bounds__(kThreads) void k_table_insert_dev(const uint64_t *__restrict__ keys,
+                                                               int64_t n,
+                                                               const int32_t *__restrict__ levels,
+                                                               uint4 *__restrict__ table,
+                                                               uint64_t mask, int shift) {
+  const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (s >= n) return;
+  const int n_levels = *levels;
+  for (int l = 0; l < n_levels; ++l) {
+    if (!is_run_start(keys, s, l)) continue;
+    const int sh = 3 * l;
+    const uint64_t key = keys[s] >> sh;
+    int64_t lo = s, step = 1, hi;
+    for (;;) {
+      hi = lo + step;
+      if (hi >= n || (keys[hi] >> sh) != key) break;
+      lo = hi;
+      step <<= 1;
+    }
+    if (hi > n) hi = n;
+    while (hi - lo > 1) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if ((keys[mid] >> sh) == key) lo = mid; else hi = mid;
+    }
+    const uint32_t count = (uint32_t)(hi - s);
+    const uint64_t tagged = key | ((uint64_t)l << kLevelShift);
+    uint64_t slot = hash_slot(tagged, shift);
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+      unsigned long long *kp = reinterpret_cast<unsigned long long *>(table + slot);
+      const unsigned long long prev = atomicCAS(kp, (unsigned long long)kEmptyKey,
+                                                (unsigned long long)tagged);
+      if (prev == (unsigned long long)kEmptyKey) {
+        uint32_t *vp = reinterpret_cast<uint32_t *>(table + slot);
+        vp[2] = (uint32_t)s;
+        vp[3] = count;
+        break;
+      }
+      slot = (slot + 1) & mask;
+    }
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_u64, dim3(blocks_for(n, 64)), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_cloud_ranges(CloudDev *clouds, int32_t n_clouds,
+                               const unsigned long long *nonfinite, hipStream_t s) {
+  hipLaunchKernelGGL(k_cloud_ranges, dim3(1), dim3(64), 0, s, clouds, n_clouds, nonfinite);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_dev_levels(const uint64_t *keys, int64_t n, int n_levels,
+                                   const unsigned long long *counts, int32_t *levels_dev,
+                                   uint4 *table, uint64_t capacity, hipStream_t s) {
+  hipLaunchKernelGGL(k_levels_fit, dim3(1), dim3(64), 0, s, counts, n_levels, capacity,
+                     levels_dev);
+  hipLaunchKernelGGL(k_table_fill, dim3(blocks_for((int64_t)capacity, 256)), dim3(256), 0, s,
+                     table, capacity);
+  int shift = 64;
+  for (uint64_t c = capacity; c > 1; c >>= 1) --shift;
+  hipLaunchKernelGGL(k_table_insert_dev, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s,
+                     keys, n, levels_dev, table, capacity - 1, shift);
+  return hipGetLastError();
+}
 
 hipError_t launch_bbox(const float *pts, const int64_t *offsets_dev, int32_t n_clouds,
                        int64_t max_cloud, uint32_t *bbox_bits, unsigned long long *nonfinite,

@@ -548,7 +548,9 @@ __device__ void merge_general(Slots &s, int &ntop, int k, uint64_t &kmax, int32_
 // scan. Returns ntop.
 __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, const double r[3],
                               const int32_t cq[3], int k, Slots &s, WaveLds &L, int lane) {
-  const int lev = g.n_levels - 1;
+  // the coarsest level in the hash; with none, the exhaustive scan
+  const int nlev = levels_of(g);
+  const int lev = nlev > 0 ? nlev - 1 : 0;
   const double cellc = ldexp(cd.cell, lev);
   int32_t c0[3];
   int32_t lmin = 0;
@@ -565,7 +567,7 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
   int ntop = 0;
   uint64_t kmax = kEmptyKey;
   int32_t imax = 0x7fffffff;
-  bool brute = lmin > kMaxRing;
+  bool brute = nlev == 0 || lmin > kMaxRing;
   const int L0 = lmin < 1 ? 1 : lmin;
   bool done = false;
   for (int ring = L0; !done && !brute; ++ring) {
@@ -670,7 +672,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
     out_keys = nullptr;
   }
   const int64_t nchunks = (qv.n + kChunk - 1) / kChunk;
-  const int nopt = 2 * g.n_levels;
+  const int nopt = 2 * levels_of(g);
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   for (int64_t task = blk * kWavesPerBlock + wv; task < nchunks;
        task += (int64_t)gridDim.x * kWavesPerBlock) {
@@ -750,7 +752,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
           lmin = max(lmin, max(-c0[a], c0[a] - (cd.dims[a] - 1)));
         }
         bool solved = false;
-        if (lmin == 0) {
+        if (lmin == 0 && nopt > 0) {
           double target = 1.05 * rho_est;
           // the query's offset in its level-0 cell, in cell units (FP32: it
           // only steers the choice of block, never the certification)

@@ -61,9 +61,18 @@ struct GridView {
   int32_t n_clouds;
   int32_t morton_bits;       // bits per axis of the level-0 key (same for all clouds)
   int64_t n_points;
-  int32_t n_levels;          // levels present in the hash (1..kMaxLevels)
+  int32_t n_levels;          // levels the first build put in the hash (1..kMaxLevels)
   int32_t hash_shift;        // 64 - log2(capacity)
+  const int32_t *levels;     // device: levels in the hash now (a rebuild
+                             // decides it on the device; 0..n_levels)
 };
+
+// Levels whose cells are in the hash (uniform; a level beyond them finds
+// nothing and must not be searched).
+__device__ __forceinline__ int levels_of(const GridView &g) {
+  const int l = g.levels ? *g.levels : g.n_levels;
+  return l < g.n_levels ? (l > 0 ? l : 0) : g.n_levels;
+}
 
 // Host-side handle contents.
 struct GridHost {
@@ -168,6 +177,17 @@ hipError_t launch_count_cells(const uint64_t *keys, int64_t n, int n_levels,
                               unsigned long long *counts, hipStream_t s);
 hipError_t launch_build_table(const uint64_t *keys, int64_t n, int n_levels, uint4 *table,
                               uint64_t capacity, hipStream_t s);
+// Rebuild helpers (kernels only, no host round trip): clear n counters;
+// recompute the clouds' sorted ranges from their non-finite counts; build the
+// table with the levels whose cells fit half of the capacity (decided on the
+// device from the per-level counts).
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s);
+hipError_t launch_cloud_ranges(CloudDev *clouds, int32_t n_clouds,
+                               const unsigned long long *nonfinite, hipStream_t s);
+hipError_t launch_table_dev_levels(const uint64_t *keys, int64_t n, int n_levels,
+                                   const unsigned long long *counts, int32_t *levels_dev,
+                                   uint4 *table, uint64_t capacity, hipStream_t s);
 
 struct QueryView {
   const void *q;            // queries, n x 3
