@@ -137,6 +137,10 @@ def parse():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--k", type=int, default=48)
     ap.add_argument("--passes", type=int, default=3)
+    ap.add_argument("--search-extra", type=int, default=None,
+                    help="extra neighbours kept for the refresh (default: tuned)")
+    ap.add_argument("--no-tune-check", action="store_true",
+                    help="skip timing the whole step for every tuning candidate")
     ap.add_argument("--cell-factor", type=float, default=None,
                     help="cell edge in units of h (default: library tuning table)")
     ap.add_argument("--cpu-sample", type=int, default=12288)
@@ -199,7 +203,7 @@ class Timer:
 
 
 def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer,
-              plane_iters=0, levin=False):
+              plane_iters=0, levin=False, search_extra=SEARCH_EXTRA):
     """Returns (ms_per_step, last outputs of pass 1, last final outputs,
     [(input, output, status) of every pass of the last step]).
     ``plane_iters``: frozen-weight steps of the reference plane in every
@@ -223,7 +227,7 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
             # neighbours; refreshed passes re-rank the lists of the pass
             # before (exact; a fresh search where not certified)
             refresh = 0 < REFRESH_FROM <= p
-            extra = SEARCH_EXTRA if 0 < REFRESH_FROM and p >= REFRESH_FROM - 1 else 0
+            extra = search_extra if 0 < REFRESH_FROM and p >= REFRESH_FROM - 1 else 0
             with ctx("refresh" if refresh else "search"):
                 grid.project(cur, k, precision, stages=1, out=nxt, status=status,
                              search_extra=extra, refresh=refresh)
@@ -379,7 +383,7 @@ def batch_loss_grad(torch, P, off, shapes, n_total):
     return grad
 
 
-def batch_fwd_bwd(api, torch, steps, warmup, keep=None):
+def batch_fwd_bwd(api, torch, steps, warmup, keep=None, tune_check=True):
     """256 clouds (~30M points, sizes log-normal, sphere / torus / height
     field, per-cloud h), k = 32, FP32: the cell edge is tuned, the grid built
     once, then [grid rebuild, search, fit, loss gradient, adjoint] is captured
@@ -392,12 +396,13 @@ def batch_fwd_bwd(api, torch, steps, warmup, keep=None):
     pts = torch.from_numpy(P).cuda()
     k = 32
     t = time.perf_counter()
-    best, ms = api.autotune_cell_factor(pts, h, k, cloud_offsets=off)
+    factors, rep = api.autotune_cells(pts, h, k, cloud_offsets=off)
     tune_s = time.perf_counter() - t
-    log("batch: tuned cell factor %.2f %s (%.1f s)" % (best, ms, tune_s))
+    log("batch: tuned cell factors per size class %s (%.1f s)" %
+        ({c: b for c, (b, _) in rep.items()}, tune_s))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    grid = api.Grid(pts, h, cloud_offsets=off, cell_size=best * h)
+    grid = api.Grid(pts, h, cloud_offsets=off, cell_size=factors * h)
     e1.record()
     torch.cuda.synchronize()
     build_ms = e0.elapsed_time(e1)
@@ -422,6 +427,33 @@ def batch_fwd_bwd(api, torch, steps, warmup, keep=None):
         body()
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    check = None
+    if tune_check:
+        # the eager step with one factor for every cloud, for each candidate:
+        # where does the per-class choice rank?
+        check = {"eager_ms_per_uniform_factor": {}, "eager_ms_tuned": eager_ms}
+        out2 = torch.empty_like(pts)
+        st2 = torch.empty((pts.shape[0],), dtype=torch.uint8, device="cuda")
+        for f in sorted(next(iter(rep.values()))[1]):
+            g2 = api.Grid(pts, h, cloud_offsets=off, cell_size=f * h)
+
+            def body2():
+                g2.rebuild(pts)
+                g2.project(pts, k, "fp32", stages=1, out=out2, status=st2)
+                g2.project(pts, k, "fp32", stages=2, out=out2, status=st2)
+                gy2 = loss_grad(out2)
+                return g2.project_backward(pts, gy2, k, "fp32", reuse_lists=True)
+            body2()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                body2()
+            torch.cuda.synchronize()
+            check["eager_ms_per_uniform_factor"][f] = (time.perf_counter() - t0) * 1000.0 / 2
+            g2.close()
+        best_u = min(check["eager_ms_per_uniform_factor"].values())
+        check["tuned_vs_best_uniform"] = eager_ms / best_u - 1.0
+        log("batch tuning check: %s" % json.dumps(check))
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -451,8 +483,10 @@ def batch_fwd_bwd(api, torch, steps, warmup, keep=None):
     return {"value": P.shape[0] / (graph_ms / 1000.0), "unit": "pts/s",
             "n_points": int(P.shape[0]), "n_clouds": int(len(h)), "k": k,
             "ms_per_step_graph": graph_ms, "ms_per_step_eager": eager_ms, "build_ms": build_ms,
-            "cell_factor": best, "autotune_ms": ms, "grads_finite": ok,
-            "graph_matches_eager": same,
+            "cell_factor_per_class": {str(c): b for c, (b, _) in rep.items()},
+            "autotune_search_ms": {str(c): m for c, (_, m) in rep.items()},
+            "autotune_s": tune_s, "grads_finite": ok,
+            "graph_matches_eager": same, "tuning_check": check,
             "step": "grid rebuild + search + fit + loss gradient + adjoint, one graph replay"}
 
 
@@ -697,14 +731,38 @@ def main():
     P, hfield = synth.heightfield(args.n, sigma=1e-3, seed=3, return_field=True)
     h = synth.mean_nn_h(P)
     log("cloud %d pts generated, h = %.6g (%.1f s)" % (args.n, h, time.perf_counter() - t))
-    cf = args.cell_factor if args.cell_factor is not None else default_cell_factor(args.k)
-    cell = cf * h
     pts = torch.from_numpy(P).cuda()
     torch.cuda.synchronize()
+    # the tuner (outside the timed steps): the cell edge from full searches
+    # of every candidate grid, then the extra neighbours of the refresh from
+    # the two searches of passes 2 and 3
+    tuning = {}
+    t = time.perf_counter()
+    if args.cell_factor is None:
+        factors, rep = api.autotune_cells(pts, h, args.k)
+        cf = float(factors[0])
+        tuning["cell_factor"] = {"pick": cf, "search_ms": rep[0][1]}
+    else:
+        cf = args.cell_factor
+    cell = cf * h
+    extra = args.search_extra
+    if extra is None:
+        gt = api.Grid(pts, h, cell_size=cell)
+        q0 = pts.double()
+        o1 = torch.empty_like(q0)
+        st1 = torch.empty((args.n,), dtype=torch.uint8, device="cuda")
+        gt.project(q0, args.k, "fp32", out=o1, status=st1)
+        extra, extra_ms = api.autotune_search_extra(gt, o1, args.k)
+        tuning["search_extra"] = {"pick": extra, "two_searches_ms": extra_ms}
+        del gt, q0, o1, st1
+    tuning["tuner_s"] = time.perf_counter() - t
+    log("tuned: cell factor %.2f, search extra %d (%.1f s) %s" %
+        (cf, extra, tuning["tuner_s"], json.dumps(tuning)))
 
     timer = Timer(torch)
     ms32, first32, out32, io32 = run_steps(api, torch, pts, h, args.k, args.passes, "fp32",
-                                           cell, args.steps, args.warmup, timer)
+                                           cell, args.steps, args.warmup, timer,
+                                           search_extra=extra)
     br32 = {n: timer.ms(n) for n in ("build", "search", "refresh", "fit")}
     log("fp32: %.2f ms/step  build %.2f  search %.2f  refresh %.2f  fit %.2f (ms per call)" %
         (ms32, br32["build"], br32["search"], br32["refresh"], br32["fit"]))
@@ -716,7 +774,8 @@ def main():
     if not args.no_fp64:
         timer64 = Timer(torch)
         ms64, first64, _, io64 = run_steps(api, torch, pts, h, args.k, args.passes, "fp64",
-                                           cell, max(1, args.steps // 2), 1, timer64)
+                                           cell, max(1, args.steps // 2), 1, timer64,
+                                           search_extra=extra)
         br64 = {n: timer64.ms(n) for n in ("build", "search", "refresh", "fit")}
         log("fp64: %.2f ms/step  build %.2f  search %.2f  refresh %.2f  fit %.2f" %
             (ms64, br64["build"], br64["search"], br64["refresh"], br64["fit"]))
@@ -764,6 +823,30 @@ def main():
            "fp64_path": fp64,
            "roofline": roof,
            "fit_roofline": fit_roof}
+
+    if not args.no_tune_check and "cell_factor" in tuning:
+        # the whole step for every candidate: does the tuner's pick rank as
+        # it does in the full runs?
+        chk = {"step_ms_per_cell_factor": {}, "step_ms_per_search_extra": {}}
+        for f in tuning["cell_factor"]["search_ms"]:
+            ms_f = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", f * h, 2, 1,
+                             Timer(torch), search_extra=extra)[0]
+            chk["step_ms_per_cell_factor"][f] = ms_f
+        if "search_extra" in tuning:
+            for e in tuning["search_extra"]["two_searches_ms"]:
+                ms_e = run_steps(api, torch, pts, h, args.k, args.passes, "fp32", cell, 2, 1,
+                                 Timer(torch), search_extra=e)[0]
+                chk["step_ms_per_search_extra"][e] = ms_e
+        for key, pick in (("step_ms_per_cell_factor", cf), ("step_ms_per_search_extra", extra)):
+            d = chk[key]
+            if d:
+                best = min(d.values())
+                chk[key + "_pick_vs_best"] = d[pick] / best - 1.0 if pick in d else None
+        tuning["full_step_check"] = chk
+        log("tuning check: %s" % json.dumps(chk))
+    res["tuning"] = tuning
+    res["config"]["cell_factor_tuned"] = cf
+    res["config"]["search_extra_tuned"] = extra
 
     first_ps = None
     if args.plane_iters > 0:

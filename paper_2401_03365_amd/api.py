@@ -292,11 +292,12 @@ class Grid:
 
 def autotune_cell_factor(points: torch.Tensor, h, k: int, cloud_offsets=None,
                          candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0),
-                         stride: int = 16):
-    """Measures the neighbour search over a sample of 1/``stride`` of the
-    points (runs of 256 consecutive points of each candidate grid's Morton
-    order) for each candidate cell edge (factor x h) and returns
-    (best factor, {factor: ms})."""
+                         stride: int = 1):
+    """Measures the neighbour search for each candidate cell edge (factor x
+    h) and returns (best factor, {factor: ms}). ``stride`` 1 (the default)
+    times the search over every point (its ranking is that of the full run);
+    a larger stride samples 1/stride of them (runs of 256 consecutive points
+    of each candidate grid's Morton order)."""
     lib = _abi.load()
     _check_points(points, "points")
     n = points.shape[0]
@@ -317,6 +318,74 @@ def autotune_cell_factor(points: torch.Tensor, h, k: int, cloud_offsets=None,
                                  ms.ctypes.data_as(ctypes.c_void_p))
     _abi.check(code, "mls_autotune_cell")
     return best.value, {float(c): float(t) for c, t in zip(cand, ms)}
+
+
+SIZE_CLASSES = (20_000, 80_000, 250_000)  # upper bounds of the cloud-size classes
+
+
+def size_class(n: int) -> int:
+    return int(np.searchsorted(np.asarray(SIZE_CLASSES), n, side="right"))
+
+
+def autotune_cells(points: torch.Tensor, h, k: int, cloud_offsets=None,
+                   candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0)):
+    """Cell edge factor per cloud: one factor for a single cloud; for a batch,
+    one per cloud-size class (clouds below 20k, 80k, 250k points and above),
+    each measured on that class's clouds alone (full searches). Returns
+    (per-cloud factors (n_clouds,), {class: (best, {factor: ms})})."""
+    if cloud_offsets is None:
+        best, ms = autotune_cell_factor(points, h, k, candidates=candidates)
+        return np.array([best]), {0: (best, ms)}
+    off = np.asarray(cloud_offsets, dtype=np.int64)
+    hh = np.broadcast_to(np.asarray(h, dtype=np.float64), (len(off) - 1,))
+    sizes = np.diff(off)
+    cls = np.array([size_class(int(n)) for n in sizes])
+    factors = np.empty(len(sizes))
+    report = {}
+    for c in np.unique(cls):
+        ids = np.nonzero(cls == c)[0]
+        parts = [points[off[i]:off[i + 1]] for i in ids]
+        sub = torch.cat(parts).contiguous()
+        sub_off = np.concatenate([[0], np.cumsum(sizes[ids])])
+        best, ms = autotune_cell_factor(sub, hh[ids], k, cloud_offsets=sub_off,
+                                        candidates=candidates)
+        factors[ids] = best
+        report[int(c)] = (best, ms)
+        del sub
+    return factors, report
+
+
+def autotune_search_extra(grid: Grid, queries: torch.Tensor, k: int, precision: str = "fp32",
+                          candidates: Sequence[int] = (8, 12, 16, 24)):
+    """Extra neighbours a search keeps for the refresh of the pass after it
+    (iterated passes): for each candidate, one pass on ``queries`` (search
+    keeping the extras, fit), then the next pass's refreshed search from its
+    outputs; the time of the two searches is measured (HIP events, second of
+    two runs). Returns (best, {extra: ms})."""
+    n = queries.shape[0]
+    out = torch.empty_like(queries)
+    nxt = torch.empty_like(queries)
+    st = torch.empty((n,), dtype=torch.uint8, device=queries.device)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    res = {}
+    for extra in candidates:
+        extra = int(min(extra, _abi.MLS_MAX_K - k))
+        for _ in range(2):
+            e0.record()
+            grid.project(queries, k, precision, stages=1, out=out, status=st,
+                         search_extra=extra)
+            e1.record()
+            grid.project(queries, k, precision, stages=2, out=out, status=st,
+                         search_extra=extra)
+            e2.record()
+            grid.project(out, k, precision, stages=1, out=nxt, status=st, search_extra=extra,
+                         refresh=True)
+            e3 = torch.cuda.Event(enable_timing=True)
+            e3.record()
+            torch.cuda.synchronize()
+        res[extra] = e0.elapsed_time(e1) + e2.elapsed_time(e3)
+    best = min(res, key=res.get)
+    return best, res
 
 
 def build_grid(points, h, cloud_offsets=None, cell_size=None) -> Grid:
