@@ -260,6 +260,18 @@ mls_status mls_get_cloud_grid(const mls_grid *grid, int32_t c, double origin[3],
 mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
                                   const int32_t **inverse_perm);
 
+/* The grid's cell table (device pointers into the workspace, for the
+ * caller's inspection): `capacity` slots of 16 bytes, each {tagged key low
+ * word, high word, first sorted position, end sorted position} (the cell
+ * holds sorted points [first, end)), empty slots with key ~0. A tagged key is
+ * the level-l cell key (the level-0 key shifted right by 3 l) with l in bits
+ * 60..62; a key sits at its home slot, the top log2(capacity) bits of
+ * key * 0x9e3779b97f4a7c15 (mod 2^64), or the first free slot after it
+ * (linear probing, wrapping). *levels (device int32) is the number of levels
+ * in the table, 0 to 8, which a rebuild decides on the device. */
+mls_status mls_grid_cell_table(const mls_grid *grid, const void **table, int64_t *capacity,
+                               const int32_t **levels);
+
 /* ---- projection --------------------------------------------------------
  * Queries belong to clouds. query_offsets (host, n_clouds+1, ascending,
  * spanning n_queries) gives each cloud's contiguous query range; NULL means

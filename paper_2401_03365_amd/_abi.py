@@ -56,6 +56,8 @@ SIGNATURES = {
     "mls_get_grid_info": (_ST, [_P, ctypes.POINTER(MlsGridInfo)]),
     "mls_get_cloud_grid": (_ST, [_P, _I32, _P, _P, _P]),
     "mls_grid_sorted_points": (_ST, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "mls_grid_cell_table": (_ST, [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(_P)]),
     "mls_project_workspace_bytes": (_SZ, [_P, _I32, _I64]),
     "mls_project_backward_workspace_bytes": (_SZ, [_P, _I32, _I64, _I32]),
     "mls_autotune_workspace_bytes": (_SZ, [_I64, _I32, _I32, _I32]),

@@ -127,6 +127,21 @@ class Grid:
         ip = self.workspace[o2:o2 + 4 * self.n_points].view(torch.int32)
         return pts, ip
 
+    def cell_table(self):
+        """(slots int64 (capacity, 2) view: [tagged key, first | end << 32],
+        levels in the table) of the grid's cell hash."""
+        tab = ctypes.c_void_p()
+        cap = ctypes.c_int64()
+        lev = ctypes.c_void_p()
+        _abi.check(_abi.load().mls_grid_cell_table(self._handle, ctypes.byref(tab),
+                                                   ctypes.byref(cap), ctypes.byref(lev)),
+                   "mls_grid_cell_table")
+        base = self.workspace.data_ptr()
+        o1, o2 = tab.value - base, lev.value - base
+        slots = self.workspace[o1:o1 + 16 * cap.value].view(torch.int64).view(-1, 2)
+        levels = int(self.workspace[o2:o2 + 4].view(torch.int32).item())
+        return slots, levels
+
     # ---- workspace --------------------------------------------------------
     def _proj_workspace(self, k: int, n: int) -> torch.Tensor:
         """One cached workspace for search, fit and adjoint (sized for the

@@ -38,7 +38,7 @@ uint64_t next_pow2(uint64_t x) {
 // Byte layout of the grid workspace.
 struct GridLayout {
   size_t pts, inv_perm, keys_a, keys_b, vals_a, vals_b, radix, table, clouds, offsets, bbox,
-      nonfinite, counter, levels, total;
+      bbox_part, nonfinite, counter, levels, total;
   uint64_t table_cap_max;
 };
 
@@ -58,6 +58,7 @@ GridLayout grid_layout(int64_t n, int32_t c) {
   L.clouds = take(sizeof(mls::CloudDev) * (size_t)c);
   L.offsets = take(8 * ((size_t)c + 1));
   L.bbox = take(24 * (size_t)c);
+  L.bbox_part = take(32 * (size_t)std::max<int64_t>(mls::kBboxPartsMax, c));
   L.nonfinite = take(8 * (size_t)c);
   L.counter = take(64);
   L.levels = take(64);  // levels in the table after a rebuild (device)
@@ -375,7 +376,8 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   } while (0)
   STEP(hipMemcpyAsync(offsets_dev, gh.offsets, 8 * ((size_t)n_clouds + 1),
                       hipMemcpyHostToDevice, s));
-  STEP(mls::launch_bbox(points, offsets_dev, n_clouds, max_cloud, bbox, nonfin, s));
+  STEP(mls::launch_bbox(points, offsets_dev, n_clouds, max_cloud, (uint4 *)(ws + L.bbox_part),
+                        bbox, nonfin, s));
   STEP(hipMemcpyAsync(bbox_h, bbox, 24 * (size_t)n_clouds, hipMemcpyDeviceToHost, s));
   STEP(hipMemcpyAsync(nonfin_h, nonfin, 8 * (size_t)n_clouds, hipMemcpyDeviceToHost, s));
   STEP(hipStreamSynchronize(s));
@@ -434,7 +436,7 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
   const int32_t *svals = in_alt ? vals_b : vals_a;
   STEP(mls::launch_gather(points, svals, n_points, pts, inv_perm, s));
   STEP(hipMemsetAsync(counter, 0, 8 * mls::kMaxLevels, s));
-  STEP(mls::launch_count_cells(skeys, n_points, mls::kMaxLevels, counter, s));
+  STEP(mls::launch_count_cells(skeys, n_points, counter, s));
   unsigned long long level_cells[mls::kMaxLevels] = {};
   STEP(hipMemcpyAsync(level_cells, counter, 8 * mls::kMaxLevels, hipMemcpyDeviceToHost, s));
   STEP(hipStreamSynchronize(s));
@@ -461,9 +463,9 @@ mls_status mls_build_grid(const float *points, int64_t n_points, const int64_t *
     }
   }
   const unsigned long long ncells = level_cells[0];
-  STEP(mls::launch_build_table(skeys, n_points, n_levels, table, cap, s));
   int32_t *levels_dev = (int32_t *)(ws + L.levels);
   STEP(mls::launch_set_i32(levels_dev, n_levels, s));
+  STEP(mls::launch_build_table(skeys, n_points, levels_dev, table, cap, s));
 #undef STEP
 
   gh.view.pts = pts;
@@ -523,7 +525,8 @@ mls_status mls_rebuild_grid(mls_grid *grid, const float *points, void *stream) {
   // lists that searches on this grid left in workspaces hold the old sorted
   // positions: no later stage may continue from them
   forget_grid(grid);
-  MLS_HIP(mls::launch_bbox(points, offsets_dev, C, max_cloud, bbox, nonfin, s));
+  MLS_HIP(mls::launch_bbox(points, offsets_dev, C, max_cloud, (uint4 *)(ws + L.bbox_part), bbox,
+                           nonfin, s));
   MLS_HIP(mls::launch_cloud_ranges(clouds, C, nonfin, s));
   MLS_HIP(mls::launch_keys(points, clouds, C, max_cloud, gh.view.morton_bits, keys_a, vals_a, s));
   bool in_alt = false;
@@ -533,7 +536,7 @@ mls_status mls_rebuild_grid(mls_grid *grid, const float *points, void *stream) {
   const int32_t *svals = in_alt ? vals_b : vals_a;
   MLS_HIP(mls::launch_gather(points, svals, n, pts, inv_perm, s));
   MLS_HIP(mls::launch_clear_u64(counter, mls::kMaxLevels, s));
-  MLS_HIP(mls::launch_count_cells(skeys, n, gh.view.n_levels, counter, s));
+  MLS_HIP(mls::launch_count_cells(skeys, n, counter, s));
   MLS_HIP(mls::launch_table_dev_levels(skeys, n, gh.view.n_levels, counter, levels, table,
                                        (uint64_t)gh.hash_capacity, s));
   return MLS_OK;
@@ -580,6 +583,15 @@ mls_status mls_grid_sorted_points(const mls_grid *grid, const void **xyzw,
   if (!grid || !xyzw || !inverse_perm) return MLS_ERR_INVALID_ARGUMENT;
   *xyzw = grid->g.view.pts;
   *inverse_perm = grid->g.view.inv_perm;
+  return MLS_OK;
+}
+
+mls_status mls_grid_cell_table(const mls_grid *grid, const void **table, int64_t *capacity,
+                               const int32_t **levels) {
+  if (!grid || !table || !capacity || !levels) return MLS_ERR_INVALID_ARGUMENT;
+  *table = grid->g.view.table;
+  *capacity = grid->g.hash_capacity;
+  *levels = grid->g.view.levels;
   return MLS_OK;
 }
 

@@ -55,7 +55,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
 struct GridView {
   const float4 *pts;         // sorted points, w = original index bits
   const int32_t *inv_perm;   // original index -> sorted position
-  const uint4 *table;        // hash slots: {key lo, key hi, start, count}, all levels
+  const uint4 *table;        // hash slots: {key lo, key hi, start, end}, all levels
   const CloudDev *clouds;    // n_clouds entries
   uint64_t hash_mask;        // capacity - 1
   int32_t n_clouds;
@@ -139,9 +139,9 @@ __device__ __forceinline__ int2 lookup_cell(const GridView &g, uint64_t key) {
     uint64_t k = (uint64_t)e.x | ((uint64_t)e.y << 32);
     if (k == key) {
       // a cell range always lies inside the sorted array
-      const int64_t st = (int64_t)e.z, ct = (int64_t)e.w;
-      if (st + ct > g.n_points) return make_int2(0, 0);
-      return make_int2((int)st, (int)ct);
+      const int64_t st = (int64_t)e.z, en = (int64_t)e.w;
+      if (en < st || en > g.n_points) return make_int2(0, 0);
+      return make_int2((int)st, (int)(en - st));
     }
     if (k == kEmptyKey) return make_int2(0, 0);
     slot = (slot + 1) & g.hash_mask;
@@ -158,9 +158,13 @@ __device__ __forceinline__ int64_t cell_coord(double x, double origin, double in
 
 // ---- host launchers (defined in the .hip files) -----------------------------
 namespace mls {
+// Bounding boxes: blocks per cloud write partial records (32 B each) that a
+// second kernel reduces; at most max(kBboxPartsMax, n_clouds) records.
+constexpr int kBboxPartsMax = 8192;
+int bbox_parts(int64_t max_cloud, int32_t n_clouds);
 hipError_t launch_bbox(const float *pts, const int64_t *offsets_dev, int32_t n_clouds,
-                       int64_t max_cloud, uint32_t *bbox_bits, unsigned long long *nonfinite,
-                       hipStream_t s);
+                       int64_t max_cloud, uint4 *partial, uint32_t *bbox_bits,
+                       unsigned long long *nonfinite, hipStream_t s);
 hipError_t launch_keys(const float *pts, const CloudDev *clouds, int32_t n_clouds,
                        int64_t max_cloud, int32_t bits, uint64_t *keys, int32_t *vals,
                        hipStream_t s);
@@ -173,10 +177,11 @@ hipError_t radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, i
                             hipStream_t s);
 hipError_t launch_gather(const float *pts, const int32_t *vals, int64_t n, float4 *sorted,
                          int32_t *inv_perm, hipStream_t s);
-hipError_t launch_count_cells(const uint64_t *keys, int64_t n, int n_levels,
-                              unsigned long long *counts, hipStream_t s);
-hipError_t launch_build_table(const uint64_t *keys, int64_t n, int n_levels, uint4 *table,
-                              uint64_t capacity, hipStream_t s);
+hipError_t launch_count_cells(const uint64_t *keys, int64_t n, unsigned long long *counts,
+                              hipStream_t s);
+// Fills the table and inserts the cells of its first *levels_dev levels.
+hipError_t launch_build_table(const uint64_t *keys, int64_t n, const int32_t *levels_dev,
+                              uint4 *table, uint64_t capacity, hipStream_t s);
 // Rebuild helpers (kernels only, no host round trip): clear n counters;
 // recompute the clouds' sorted ranges from their non-finite counts; build the
 // table with the levels whose cells fit half of the capacity (decided on the

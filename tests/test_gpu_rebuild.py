@@ -20,6 +20,7 @@ import torch
 
 from paper_2401_03365_amd import synth
 from tests.parity import check_projection
+from tests.test_gpu_grid import check_table, grid_keys
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +61,8 @@ def test_rebuild_on_moved_points_is_exact(orc, precision):
     M[100:103] = np.nan                # non-finite
     Mt = torch.from_numpy(M).cuda()
     g.rebuild(Mt)
+    if precision == "fp64":  # the rebuilt order and cell table, from the grid's geometry
+        check_table(g, grid_keys(g, M, np.array([0, M.shape[0]]))[0])
     Q = M[rng.choice(M.shape[0], 4000, replace=False)].astype(np.float64)
     Q = Q[np.isfinite(Q).all(axis=1)]
     Qt = torch.from_numpy(Q).cuda()
@@ -91,6 +94,7 @@ def test_rebuild_with_levels_left_out_stays_exact(orc):
     c = np.clip(np.floor((spread.astype(np.float64) - origin) / cell), 0, np.array(dims) - 1)
     assert len(np.unique(c, axis=0)) > cap // 2
     g.rebuild(torch.from_numpy(spread).cuda())
+    check_table(g, grid_keys(g, spread, np.array([0, spread.shape[0]]))[0], levels=0)
     Q = spread[:300].astype(np.float64)
     nbr = g.knn(torch.from_numpy(Q).cuda(), 16)
     torch.cuda.synchronize()
