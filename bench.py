@@ -45,6 +45,7 @@ FP64_PEAK_TFLOPS = 78.6
 # (59 % certified); the second moves them by 0.04 h.
 SEARCH_EXTRA = 16
 REFRESH_FROM = 2  # 0-based pass index of the first refreshed pass
+SLOT_ORDER = True  # iterated passes keep intermediate points in sorted order
 FIT_FLOPS_PER_NEIGHBOUR = 108 + 2
 FIT_FP64_FLOPS_PER_QUERY = 1000
 # one step of the reference plane: the pass-1 moments again with the weights
@@ -139,6 +140,8 @@ def parse():
     ap.add_argument("--passes", type=int, default=3)
     ap.add_argument("--search-extra", type=int, default=None,
                     help="extra neighbours kept for the refresh (default: tuned)")
+    ap.add_argument("--caller-order", action="store_true",
+                    help="keep intermediate points of iterated passes in the caller's order")
     ap.add_argument("--no-tune-check", action="store_true",
                     help="skip timing the whole step for every tuning candidate")
     ap.add_argument("--cell-factor", type=float, default=None,
@@ -203,18 +206,22 @@ class Timer:
 
 
 def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, timer,
-              plane_iters=0, levin=False, search_extra=SEARCH_EXTRA):
+              plane_iters=0, levin=False, search_extra=SEARCH_EXTRA, slot_order=None):
     """Returns (ms_per_step, last outputs of pass 1, last final outputs,
-    [(input, output, status) of every pass of the last step]).
-    ``plane_iters``: frozen-weight steps of the reference plane in every
-    fit; ``levin``: Levin's reference plane in every fit."""
+    [(input, output, status) of every pass of the last step], all in the
+    caller's order). ``plane_iters``: frozen-weight steps of the reference
+    plane in every fit; ``levin``: Levin's reference plane in every fit;
+    ``slot_order``: the passes between the first and the last keep their
+    points in the grid's sorted order (default SLOT_ORDER)."""
+    if slot_order is None:
+        slot_order = SLOT_ORDER
     q0 = pts.double()
-    first = None
     out = None
     passes_io = []
+    grid = None
 
     def step(record):
-        nonlocal first, out, passes_io
+        nonlocal out, passes_io, grid
         passes_io = []
         ctx = timer.span if record else (lambda name: _Null())
         with ctx("build"):
@@ -228,15 +235,20 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
             # before (exact; a fresh search where not certified)
             refresh = 0 < REFRESH_FROM <= p
             extra = search_extra if 0 < REFRESH_FROM and p >= REFRESH_FROM - 1 else 0
+            # intermediate points in sorted order: every pass but the first
+            # reads its queries in sequence, every pass but the last writes
+            # its results in sequence
+            s_in = slot_order and p > 0
+            s_out = slot_order and p < passes - 1
+            so = (1 if s_in else 0) | (2 if s_out else 0)
             with ctx("refresh" if refresh else "search"):
                 grid.project(cur, k, precision, stages=1, out=nxt, status=status,
-                             search_extra=extra, refresh=refresh)
+                             search_extra=extra, refresh=refresh, slot_order=so)
             with ctx("fit"):
                 grid.project(cur, k, precision, stages=2, out=nxt, status=status,
-                             search_extra=extra, plane_iters=plane_iters, levin=levin)
-            if p == 0:
-                first = nxt
-            passes_io.append((cur, nxt, status))
+                             search_extra=extra, plane_iters=plane_iters, levin=levin,
+                             slot_order=so)
+            passes_io.append((cur, nxt, status, s_in, s_out))
             cur = nxt
         out = cur
         return grid
@@ -250,6 +262,18 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
         step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # rows of the last step in the caller's order (outside the timed region)
+    rows = grid.caller_rows()
+
+    def caller(x, in_slots):
+        if not in_slots:
+            return x
+        y = torch.empty_like(x)
+        y[rows] = x
+        return y
+
+    passes_io = [(caller(c, si), caller(n, so), caller(st, so)) for c, n, st, si, so in passes_io]
+    first = passes_io[0][1] if passes_io else None
     return (t1 - t0) * 1000.0 / steps, first, out, passes_io
 
 
@@ -704,7 +728,9 @@ def quality_table(api, torch):
 
 
 def main():
+    global SLOT_ORDER
     args = parse()
+    SLOT_ORDER = not args.caller_order
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X "
               "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
@@ -816,7 +842,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": "heightfield-10M-k48-3pass", "n_points": args.n, "k": args.k,
                       "passes": args.passes, "precision": "fp32-moments+fp64-solves",
-                      "h": h, "cell_size": cell, "step": "grid build + %d passes" % args.passes},
+                      "h": h, "cell_size": cell, "step": "grid build + %d passes" % args.passes,
+                      "intermediate_order": "caller" if args.caller_order else "sorted"},
            "breakdown_ms": br32,
            "value_excl_build": args.n * args.passes /
            ((ms32 - br32["build"]) / 1000.0),
@@ -842,6 +869,13 @@ def main():
             if d:
                 best = min(d.values())
                 chk[key + "_pick_vs_best"] = d[pick] / best - 1.0 if pick in d else None
+        # the same step with every pass in the caller's order
+        chk["step_ms_caller_order"] = run_steps(api, torch, pts, h, args.k, args.passes, "fp32",
+                                                cell, 2, 1, Timer(torch), search_extra=extra,
+                                                slot_order=False)[0]
+        chk["step_ms_sorted_order"] = run_steps(api, torch, pts, h, args.k, args.passes, "fp32",
+                                                cell, 2, 1, Timer(torch), search_extra=extra,
+                                                slot_order=True)[0]
         tuning["full_step_check"] = chk
         log("tuning check: %s" % json.dumps(chk))
     res["tuning"] = tuning

@@ -137,7 +137,28 @@ typedef struct {
                                gives MLS_PT_NO_MINIMUM. Excludes plane_iters
                                (MLS_ERR_INVALID_ARGUMENT); forward only
                                (the adjoint returns MLS_ERR_UNSUPPORTED). */
+  int32_t slot_order;       /* mls_slot_order bits; 0 = the caller's order.
+                               For queries aligned with the grid's points
+                               only (query_offsets NULL, n_queries ==
+                               n_points; else MLS_ERR_INVALID_ARGUMENT):
+                               MLS_SLOT_QUERIES reads the query of sorted
+                               position p (mls_grid_sorted_points) at
+                               queries[p], MLS_SLOT_OUTPUTS writes its output,
+                               status and list at p. Iterated passes keep
+                               their intermediate points in that order and
+                               read and write memory in sequence; the last
+                               pass returns the caller's order (QUERIES
+                               alone). With exactly one of the two bits,
+                               out_points must not alias queries. Not with
+                               ball = 2 nor in the adjoint
+                               (MLS_ERR_UNSUPPORTED). */
 } mls_params;
+
+/* Bits of mls_params.slot_order. */
+typedef enum {
+  MLS_SLOT_QUERIES = 1,
+  MLS_SLOT_OUTPUTS = 2
+} mls_slot_order;
 
 /* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and
  * support counts in the workspace; a later call with MLS_STAGE_FIT on the

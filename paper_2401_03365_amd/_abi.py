@@ -30,12 +30,16 @@ _I32, _I64, _F64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.
 _ST = ctypes.c_int
 
 
+MLS_SLOT_QUERIES = 1
+MLS_SLOT_OUTPUTS = 2
+
+
 class MlsParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("support_radius_h", ctypes.c_double), ("min_support", ctypes.c_int32),
                 ("stages", ctypes.c_int32), ("search_extra", ctypes.c_int32),
                 ("plane_iters", ctypes.c_int32), ("ball", ctypes.c_int32),
-                ("levin", ctypes.c_int32)]
+                ("levin", ctypes.c_int32), ("slot_order", ctypes.c_int32)]
 
 
 class MlsGridInfo(ctypes.Structure):

@@ -127,6 +127,13 @@ class Grid:
         ip = self.workspace[o2:o2 + 4 * self.n_points].view(torch.int32)
         return pts, ip
 
+    def caller_rows(self) -> torch.Tensor:
+        """int64 (n,): the point index of each sorted position, so that
+        x_caller[caller_rows()] = x_sorted converts rows in the grid's sorted
+        order (slot_order) to the caller's."""
+        pts, _ = self.sorted_points()
+        return pts[:, 3].contiguous().view(torch.int32).long()
+
     def cell_table(self):
         """(slots int64 (capacity, 2) view: [tagged key, first | end << 32],
         levels in the table) of the grid's cell hash."""
@@ -173,21 +180,22 @@ class Grid:
         return (nbr, keys) if return_keys else nbr
 
     def _params(self, k, precision, support_radius_h, min_support, stages=0, search_extra=0,
-                plane_iters=0, ball=False, levin=False):
+                plane_iters=0, ball=False, levin=False, slot_order=0):
         if precision not in PRECISIONS:
             raise ValueError("precision must be 'fp32' or 'fp64'")
         return _abi.MlsParams(k=int(k), precision=PRECISIONS[precision],
                               support_radius_h=float(support_radius_h),
                               min_support=int(min_support), stages=int(stages),
                               search_extra=int(search_extra), plane_iters=int(plane_iters),
-                              ball=int(ball), levin=int(bool(levin)))
+                              ball=int(ball), levin=int(bool(levin)),
+                              slot_order=int(slot_order))
 
     def project(self, queries: torch.Tensor, k: int, precision: str = "fp32",
                 query_offsets=None, return_neighbors=False, out: Optional[torch.Tensor] = None,
                 support_radius_h: float = 3.0, min_support: int = 3, stages: int = 0,
                 status: Optional[torch.Tensor] = None, search_extra: int = 0,
                 refresh: bool = False, plane_iters: int = 0, ball: bool = False,
-                geometry: bool = False, levin: bool = False):
+                geometry: bool = False, levin: bool = False, slot_order: int = 0):
         """One MLS projection pass. Returns (out, status[, neighbours]).
         ``stages``: 0 = search and fit, 1 = search only (lists stay in the
         grid's workspace), 2 = fit only from the preceding search.
@@ -204,13 +212,16 @@ class Grid:
         the whole list lies inside it; 2: every cloud point within that
         radius, no count cap (k unused, no lists returned); ``geometry``: also return the surface
         normal (n, 3) and the mean and Gaussian curvature (n, 2) at each
-        output, after the status: (out, status, normals, curvatures[, nbr])."""
+        output, after the status: (out, status, normals, curvatures[, nbr]).
+        ``slot_order`` (queries aligned with the points only): bit 1 reads
+        the query of sorted position p at row p, bit 2 writes its results at
+        row p (``caller_rows`` maps rows in that order to point indices)."""
         _check_points(queries, "queries", (torch.float32, torch.float64))
         n = queries.shape[0]
         if refresh:
             stages = (stages or (_abi.MLS_STAGE_SEARCH | _abi.MLS_STAGE_FIT)) | _abi.MLS_STAGE_REFRESH
         params = self._params(k, precision, support_radius_h, min_support, stages, search_extra,
-                              plane_iters, ball, levin)
+                              plane_iters, ball, levin, slot_order)
         if out is None:
             out = torch.empty_like(queries)
         if status is None:

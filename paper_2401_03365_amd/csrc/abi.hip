@@ -643,6 +643,8 @@ mls_status prepare_queries(const mls_grid *grid, int32_t k, int32_t k_list, cons
   qv->aligned = aligned ? 1 : 0;
   qv->qcloud = nullptr;
   qv->kstride = k_list;
+  qv->slot_in = 0;
+  qv->slot_out = 0;
   if (C > 1 && n > 0) {
     // queries aligned with the points take the grid's device offsets (no
     // host copy, so the call can be captured in a graph); explicit query
@@ -720,8 +722,19 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
       params->search_extra < 0 || params->search_extra > MLS_MAX_K ||
       params->plane_iters < 0 || params->plane_iters > MLS_MAX_PLANE_ITERS ||
       params->ball < 0 || params->ball > 2 || (params->levin != 0 && params->levin != 1) ||
-      (params->levin && params->plane_iters))
+      (params->levin && params->plane_iters) || params->slot_order < 0 || params->slot_order > 3)
     return MLS_ERR_INVALID_ARGUMENT;
+  if (params->slot_order) {
+    // sorted order exists for queries aligned with the grid's points only
+    if (!grid || query_offsets || n_queries != grid->g.n_points) {
+      snprintf(g_last_error, sizeof g_last_error,
+               "slot_order needs queries aligned with the grid's points");
+      return MLS_ERR_INVALID_ARGUMENT;
+    }
+    if (params->slot_order != 3 && n_queries > 0 && queries == out_points)
+      return MLS_ERR_INVALID_ARGUMENT;
+    if (params->ball == 2) return MLS_ERR_UNSUPPORTED;
+  }
   const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
   if ((stages & MLS_STAGE_REFRESH) && !(stages & MLS_STAGE_SEARCH))
     return MLS_ERR_INVALID_ARGUMENT;
@@ -771,6 +784,8 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
   mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
                                   query_offsets, workspace, workspace_bytes, sort, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
+  qv.slot_in = (params->slot_order & MLS_SLOT_QUERIES) ? 1 : 0;
+  qv.slot_out = (params->slot_order & MLS_SLOT_OUTPUTS) ? 1 : 0;
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);
   uint8_t *support = (uint8_t *)(ws + L.support);
@@ -846,7 +861,8 @@ mls_status mls_project_backward(const mls_grid *grid, const mls_params *params,
   if (!(params->support_radius_h > 0.0) || !isfinite(params->support_radius_h) ||
       params->min_support < 0 || params->search_extra < 0 || params->search_extra > MLS_MAX_K)
     return MLS_ERR_INVALID_ARGUMENT;
-  if (params->plane_iters != 0 || params->ball != 0 || params->levin != 0)
+  if (params->plane_iters != 0 || params->ball != 0 || params->levin != 0 ||
+      params->slot_order != 0)
     return MLS_ERR_UNSUPPORTED;
   const int32_t k_list = params->k + params->search_extra;
   // stages: ALL = lists from `neighbors` or a fresh search; FIT = the lists a

@@ -140,6 +140,7 @@ mls_status mls_autotune_cell(const float *points, int64_t n_points, const int64_
   prm.plane_iters = 0;
   prm.ball = 0;
   prm.levin = 0;
+  prm.slot_order = 0;
   mls_status st = MLS_OK;
   float best_ms = INFINITY;
   *best_factor = candidates[0];

@@ -123,15 +123,16 @@ __global__ __launch_bounds__(64 * kBallWaves) void k_ball(GridView g, QueryView 
   const int64_t first = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBallWaves + wv;
   for (int64_t p = first; p < qv.n; p += (int64_t)gridDim.x * kBallWaves) {
     const int64_t qi = __builtin_amdgcn_readfirstlane((int)query_of_slot(g, qv, p));
+    const int64_t qo = out_index(qv, p, qi);  // where the results go
     double r[3];
-    load_query(qv, qi, r);
+    load_query(qv, in_index(qv, p, qi), r);
     const bool lead = lane == 0;
     if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]))) {
       const double o[3] = {nanv, nanv, nanv};
       if (lead) {
-        store_vec(out, qv.is_f64, qi, o);
-        status[qi] = MLS_PT_NONFINITE;
-        store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+        store_vec(out, qv.is_f64, qo, o);
+        status[qo] = MLS_PT_NONFINITE;
+        store_geometry(out_normals, out_curv, qv.is_f64, qo, o, nanv, nanv);
       }
       continue;
     }
@@ -201,10 +202,10 @@ __global__ __launch_bounds__(64 * kBallWaves) void k_ball(GridView g, QueryView 
     const uint32_t m = wave_sum_u32(m_lane);
     if ((int)m < min_support) {
       if (lead) {
-        store_vec(out, qv.is_f64, qi, r);
-        status[qi] = MLS_PT_OUTLIER;
+        store_vec(out, qv.is_f64, qo, r);
+        status[qo] = MLS_PT_OUTLIER;
         const double o[3] = {nanv, nanv, nanv};
-        store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+        store_geometry(out_normals, out_curv, qv.is_f64, qo, o, nanv, nanv);
       }
       continue;
     }
@@ -259,8 +260,8 @@ __global__ __launch_bounds__(64 * kBallWaves) void k_ball(GridView g, QueryView 
       st = MLS_PT_PLANE_ONLY;
     }
     if (lead) {
-      store_vec(out, qv.is_f64, qi, o);
-      status[qi] = st | pf.flags;
+      store_vec(out, qv.is_f64, qo, o);
+      status[qo] = st | pf.flags;
       if (out_normals || out_curv) {
         double N[3] = {pf.n[0], pf.n[1], pf.n[2]};
         double H = nanv, K = nanv;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(64 * kBallWaves) void k_ball(GridView g, QueryView 
               (2.0 * W * sqrt(W));
           K = (fxx * fyy - fxy * fxy) / (W * W);
         }
-        store_geometry(out_normals, out_curv, qv.is_f64, qi, N, H, K);
+        store_geometry(out_normals, out_curv, qv.is_f64, qo, N, H, K);
       }
     }
   }

@@ -708,14 +708,16 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       if (p < pend && ((todo >> lane) & 1)) {
         if (qv.aligned) qi = __float_as_int(g.pts[p].w);
         else qi = (int32_t)ordered_query(qv, p);
+        const int64_t qin = in_index(qv, p, qi);
         if (qv.is_f64) {
-          const double *q = (const double *)qv.q + 3 * (int64_t)qi;
+          const double *q = (const double *)qv.q + 3 * qin;
           x = q[0]; y = q[1]; z = q[2];
         } else {
-          const float *q = (const float *)qv.q + 3 * (int64_t)qi;
+          const float *q = (const float *)qv.q + 3 * qin;
           x = q[0]; y = q[1]; z = q[2];
         }
         cl = qv.qcloud ? qv.qcloud[qi] : 0;
+        qi = (int32_t)out_index(qv, p, qi);  // where the caller's lists go
       }
       wave_sync();
       Q.x[lane] = x; Q.y[lane] = y; Q.z[lane] = z;
@@ -1009,10 +1011,10 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
   else qi = ordered_query(qv, p);
   double r[3];
   if (qv.is_f64) {
-    const double *q = (const double *)qv.q + 3 * qi;
+    const double *q = (const double *)qv.q + 3 * in_index(qv, p, qi);
     r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
   } else {
-    const float *q = (const float *)qv.q + 3 * qi;
+    const float *q = (const float *)qv.q + 3 * in_index(qv, p, qi);
     r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
   }
   const double *an = anchor + 4 * p;
@@ -1125,10 +1127,10 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
       qi = __builtin_amdgcn_readfirstlane((int)qi);
       double r[3];
       if (qv.is_f64) {
-        const double *q = (const double *)qv.q + 3 * qi;
+        const double *q = (const double *)qv.q + 3 * in_index(qv, p, qi);
         r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
       } else {
-        const float *q = (const float *)qv.q + 3 * qi;
+        const float *q = (const float *)qv.q + 3 * in_index(qv, p, qi);
         r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
       }
       const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
@@ -1142,8 +1144,8 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
           slot_flag[p] = 0;
         }
         if (lane < kfit) {
-          if (out_nbr) out_nbr[qi * kfit + lane] = -1;
-          if (out_keys) out_keys[qi * kfit + lane] = bitsd(0x7ff8000000000000ull);
+          if (out_nbr) out_nbr[out_index(qv, p, qi) * kfit + lane] = -1;
+          if (out_keys) out_keys[out_index(qv, p, qi) * kfit + lane] = bitsd(0x7ff8000000000000ull);
         }
         continue;
       }
@@ -1181,8 +1183,8 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
         const uint32_t m = popc(__ballot(lane < kfit && bitsd(mk) <= rad2));
         if (lane < k) row[lane * 64] = mp;
         if (lane < kfit) {
-          if (out_nbr) out_nbr[qi * kfit + lane] = mi;
-          if (out_keys) out_keys[qi * kfit + lane] = bitsd(mk);
+          if (out_nbr) out_nbr[out_index(qv, p, qi) * kfit + lane] = mi;
+          if (out_keys) out_keys[out_index(qv, p, qi) * kfit + lane] = bitsd(mk);
         }
         if (lane == 0) support[p] = (uint8_t)m;
       }

@@ -74,24 +74,25 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
   const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (p >= qv.n) return;
   const int64_t qi = query_of_slot(g, qv, p);
+  const int64_t qo = out_index(qv, p, qi);  // where the results go
   double r[3];
-  load_query(qv, qi, r);
+  load_query(qv, in_index(qv, p, qi), r);
   if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]))) {
     const double nanv = __longlong_as_double(0x7ff8000000000000ll);
     const double o[3] = {nanv, nanv, nanv};
-    store_vec(out, qv.is_f64, qi, o);
-    status[qi] = MLS_PT_NONFINITE;
-    if (kExt) store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+    store_vec(out, qv.is_f64, qo, o);
+    status[qo] = MLS_PT_NONFINITE;
+    if (kExt) store_geometry(out_normals, out_curv, qv.is_f64, qo, o, nanv, nanv);
     return;
   }
   const int m = support[p];
   if (m < min_support) {
-    store_vec(out, qv.is_f64, qi, r);
-    status[qi] = MLS_PT_OUTLIER;
+    store_vec(out, qv.is_f64, qo, r);
+    status[qo] = MLS_PT_OUTLIER;
     if (kExt) {
       const double nanv = __longlong_as_double(0x7ff8000000000000ll);
       const double o[3] = {nanv, nanv, nanv};
-      store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+      store_geometry(out_normals, out_curv, qv.is_f64, qo, o, nanv, nanv);
     }
     return;
   }
@@ -135,11 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
       double n[3] = {pf.n[0], pf.n[1], pf.n[2]};
       double tau = pf.t;
       if (!levin_descend(g, nb, k, r, 1.0 / h, support_radius_h, mask, n, tau)) {
-        store_vec(out, qv.is_f64, qi, r);
-        status[qi] = MLS_PT_NO_MINIMUM | pf.flags | extra_flags;
+        store_vec(out, qv.is_f64, qo, r);
+        status[qo] = MLS_PT_NO_MINIMUM | pf.flags | extra_flags;
         const double nanv = __longlong_as_double(0x7ff8000000000000ll);
         const double o[3] = {nanv, nanv, nanv};
-        store_geometry(out_normals, out_curv, qv.is_f64, qi, o, nanv, nanv);
+        store_geometry(out_normals, out_curv, qv.is_f64, qo, o, nanv, nanv);
         return;
       }
       pf = plane_of(n, tau, r, h, pf.flags);
@@ -169,8 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
     for (int c = 0; c < 3; ++c) o[c] = pf.q[c];
     st = MLS_PT_PLANE_ONLY;
   }
-  store_vec(out, qv.is_f64, qi, o);
-  status[qi] = st | pf.flags | extra_flags;
+  store_vec(out, qv.is_f64, qo, o);
+  status[qo] = st | pf.flags | extra_flags;
   if (kExt && (out_normals || out_curv)) {
     const double nanv = __longlong_as_double(0x7ff8000000000000ll);
     double N[3] = {pf.n[0], pf.n[1], pf.n[2]};
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
           (2.0 * W * sqrt(W));
       K = (fxx * fyy - fxy * fxy) / (W * W);
     }
-    store_geometry(out_normals, out_curv, qv.is_f64, qi, N, H, K);
+    store_geometry(out_normals, out_curv, qv.is_f64, qo, N, H, K);
   }
 }
 

@@ -202,7 +202,19 @@ struct QueryView {
   const int32_t *qcloud;    // per query cloud id, or null (cloud 0)
   int32_t aligned;          // queries aligned with points: order from the grid
   int32_t kstride;          // entries per query in the tile lists (k + search extra)
+  int32_t slot_in;          // aligned queries given in the grid's sorted order (q[p])
+  int32_t slot_out;         // results written in the grid's sorted order (out[p])
 };
+
+// Index of slot p's query in the query array and of its results in the
+// result arrays (qi: the query's own index, the original point index for
+// aligned queries).
+__device__ __forceinline__ int64_t in_index(const QueryView &qv, int64_t p, int64_t qi) {
+  return qv.slot_in ? p : qi;
+}
+__device__ __forceinline__ int64_t out_index(const QueryView &qv, int64_t p, int64_t qi) {
+  return qv.slot_out ? p : qi;
+}
 
 // Query index of slot p < qv.n for queries that are not the grid's points:
 // the permutation of the search's sort (clamped, like list entries, so that

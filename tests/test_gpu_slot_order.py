@@ -1,0 +1,142 @@
+"""Queries and results in the grid's sorted order (slot_order): the same
+projections, bit for bit, as in the caller's order, with rows permuted by
+the sorted positions' point indices; iterated passes in that order (the
+first writing sorted rows, the middle ones reading and writing them, the
+last returning the caller's order) equal the caller-order passes; and the
+argument rules of the mode."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_03365_amd import _abi, synth
+
+pytestmark = pytest.mark.gpu
+
+Q_, O_ = 1, 2
+
+
+def api():
+    from paper_2401_03365_amd import api as a
+    return a
+
+
+def nan_eq(a, b):
+    return torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b, nan=7.0))
+
+
+def cloud(seed=81):
+    P = synth.torus(30000, sigma=0.005, n_outliers=300, seed=seed)
+    P[[5, 77, 4000]] = np.nan
+    return P
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("moved", [False, True])
+def test_slot_order_matches_caller_order(precision, moved):
+    P = cloud()
+    h = synth.mean_nn_h(P[np.isfinite(P).all(1)])
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h)
+    q = Pt.double()
+    if moved:
+        rng = np.random.default_rng(82)
+        q = q + torch.from_numpy(rng.uniform(-0.3, 0.3, P.shape) * h).cuda()
+    rows = g.caller_rows()
+    ref, rst, rnb = g.project(q, 24, precision, return_neighbors=True)
+    qs = q[rows].contiguous()
+    # results in sorted rows
+    o2, s2, n2 = g.project(q, 24, precision, return_neighbors=True, slot_order=O_)
+    assert nan_eq(o2, ref[rows]) and torch.equal(s2, rst[rows]) and torch.equal(n2, rnb[rows])
+    # queries in sorted rows, results in the caller's
+    o1, s1, n1 = g.project(qs, 24, precision, return_neighbors=True, slot_order=Q_)
+    assert nan_eq(o1, ref) and torch.equal(s1, rst) and torch.equal(n1, rnb)
+    # both
+    o3, s3, n3 = g.project(qs, 24, precision, return_neighbors=True, slot_order=Q_ | O_)
+    assert nan_eq(o3, ref[rows]) and torch.equal(s3, rst[rows]) and torch.equal(n3, rnb[rows])
+    # in place on sorted rows (calls without caller lists keep the lists in
+    # selection order, so the FP32 sums run in another order than above)
+    o4, _ = g.project(qs, 24, precision, slot_order=Q_ | O_)
+    qq = qs.clone()
+    g.project(qq, 24, precision, out=qq, slot_order=Q_ | O_)
+    assert nan_eq(qq, o4)
+    o5, _ = g.project(q, 24, precision)
+    assert nan_eq(o4, o5[rows])
+
+
+def test_iterated_passes_in_sorted_order():
+    P = synth.heightfield(60000, sigma=1e-3, seed=83)
+    h = synth.mean_nn_h(P)
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h, cell_size=1.25 * h)
+    k, extra = 32, 12
+
+    def passes(orders):
+        cur = Pt.double()
+        outs = []
+        for it, so in enumerate(orders):
+            nxt = torch.empty_like(cur)
+            st = torch.empty(P.shape[0], dtype=torch.uint8, device="cuda")
+            e = extra if it > 0 else 0
+            g.project(cur, k, "fp32", stages=1, out=nxt, status=st, search_extra=e,
+                      refresh=it == 2, slot_order=so)
+            g.project(cur, k, "fp32", stages=2, out=nxt, status=st, search_extra=e,
+                      slot_order=so)
+            outs.append((nxt, st))
+            cur = nxt
+        return outs
+
+    ref = passes([0, 0, 0])
+    got = passes([O_, Q_ | O_, Q_])
+    rows = g.caller_rows()
+    for it, ((ro, rs), (go, gs)) in enumerate(zip(ref, got)):
+        if it < 2:
+            assert nan_eq(go, ro[rows]) and torch.equal(gs, rs[rows]), it
+        else:
+            assert nan_eq(go, ro) and torch.equal(gs, rs), it
+
+
+def test_slot_order_in_a_batch():
+    parts = [synth.sphere(20000, 0.01, seed=84), synth.torus(25000, sigma=0.01, seed=85)]
+    P = np.concatenate(parts)
+    offs = np.array([0, 20000, 45000], dtype=np.int64)
+    hs = [synth.mean_nn_h(p) for p in parts]
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, hs, cloud_offsets=offs)
+    q = Pt.double()
+    ref, rst = g.project(q, 20, "fp32")
+    rows = g.caller_rows()
+    o, s = g.project(q[rows].contiguous(), 20, "fp32", slot_order=Q_ | O_)
+    assert nan_eq(o, ref[rows]) and torch.equal(s, rst[rows])
+
+
+def test_slot_order_argument_rules():
+    P = synth.sphere(5000, 0.01, seed=86)
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, synth.mean_nn_h(P))
+    q = Pt.double()
+    bad, unsup = _abi.MLS_ERR_INVALID_ARGUMENT, _abi.MLS_ERR_UNSUPPORTED
+    qq = q.clone()
+    for kw, code in ((dict(queries=q[:4000].contiguous(), slot_order=Q_), bad),  # not aligned
+                     (dict(query_offsets=[0, 5000], slot_order=O_), bad),
+                     (dict(slot_order=4), bad),
+                     (dict(queries=qq, out=qq, slot_order=Q_), bad),  # in place, orders differ
+                     (dict(ball=2, slot_order=Q_ | O_), unsup)):
+        kw = dict(kw)
+        queries = kw.pop("queries", q)
+        with pytest.raises(_abi.MLSError) as ei:
+            g.project(queries, 16, "fp32", **kw)
+        assert ei.value.code == code, kw
+    # the adjoint keeps the caller's order
+    lib = _abi.load()
+    params = g._params(16, "fp32", 3.0, 3, slot_order=Q_)
+    ws = g._proj_workspace(16, P.shape[0])
+    go = torch.zeros_like(Pt)
+    gq = torch.empty_like(Pt)
+    gp = torch.empty_like(Pt)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    code = lib.mls_project_backward(g._handle, ctypes.byref(params), p(Pt), _abi.MLS_F32,
+                                    P.shape[0], None, None, p(go), p(gq), p(gp), p(ws),
+                                    ws.numel(), None)
+    assert code == unsup
