@@ -241,6 +241,8 @@ def run_steps(api, torch, pts, h, k, passes, precision, cell, steps, warmup, tim
             s_in = slot_order and p > 0
             s_out = slot_order and p < passes - 1
             so = (1 if s_in else 0) | (2 if s_out else 0)
+            if slot_order and p == 0:
+                so |= 4  # the first pass's queries are the grid's own points
             with ctx("refresh" if refresh else "search"):
                 grid.project(cur, k, precision, stages=1, out=nxt, status=status,
                              search_extra=extra, refresh=refresh, slot_order=so)

@@ -148,7 +148,11 @@ typedef struct {
                                their intermediate points in that order and
                                read and write memory in sequence; the last
                                pass returns the caller's order (QUERIES
-                               alone). With exactly one of the two bits,
+                               alone). MLS_SLOT_OWN_POINTS takes the grid's
+                               own points as the queries (queries may be
+                               NULL; dtype still gives the outputs' type),
+                               the first pass of iterated passes. With
+                               exactly one of QUERIES and OUTPUTS,
                                out_points must not alias queries. Not with
                                ball = 2 nor in the adjoint
                                (MLS_ERR_UNSUPPORTED). */
@@ -157,7 +161,8 @@ typedef struct {
 /* Bits of mls_params.slot_order. */
 typedef enum {
   MLS_SLOT_QUERIES = 1,
-  MLS_SLOT_OUTPUTS = 2
+  MLS_SLOT_OUTPUTS = 2,
+  MLS_SLOT_OWN_POINTS = 4
 } mls_slot_order;
 
 /* Stages of mls_project. MLS_STAGE_SEARCH leaves the neighbour lists and

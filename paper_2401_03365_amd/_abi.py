@@ -32,6 +32,7 @@ _ST = ctypes.c_int
 
 MLS_SLOT_QUERIES = 1
 MLS_SLOT_OUTPUTS = 2
+MLS_SLOT_OWN_POINTS = 4
 
 
 class MlsParams(ctypes.Structure):

@@ -645,6 +645,8 @@ mls_status prepare_queries(const mls_grid *grid, int32_t k, int32_t k_list, cons
   qv->kstride = k_list;
   qv->slot_in = 0;
   qv->slot_out = 0;
+  qv->in_f64 = qv->is_f64;
+  qv->in_stride = 3;
   if (C > 1 && n > 0) {
     // queries aligned with the points take the grid's device offsets (no
     // host copy, so the call can be captured in a graph); explicit query
@@ -722,7 +724,7 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
       params->search_extra < 0 || params->search_extra > MLS_MAX_K ||
       params->plane_iters < 0 || params->plane_iters > MLS_MAX_PLANE_ITERS ||
       params->ball < 0 || params->ball > 2 || (params->levin != 0 && params->levin != 1) ||
-      (params->levin && params->plane_iters) || params->slot_order < 0 || params->slot_order > 3)
+      (params->levin && params->plane_iters) || params->slot_order < 0 || params->slot_order > 7)
     return MLS_ERR_INVALID_ARGUMENT;
   if (params->slot_order) {
     // sorted order exists for queries aligned with the grid's points only
@@ -731,9 +733,14 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
                "slot_order needs queries aligned with the grid's points");
       return MLS_ERR_INVALID_ARGUMENT;
     }
-    if (params->slot_order != 3 && n_queries > 0 && queries == out_points)
+    const bool own = (params->slot_order & MLS_SLOT_OWN_POINTS) != 0;
+    const bool q_sorted = own || (params->slot_order & MLS_SLOT_QUERIES);
+    if (!own && q_sorted != ((params->slot_order & MLS_SLOT_OUTPUTS) != 0) && n_queries > 0 &&
+        queries == out_points)
       return MLS_ERR_INVALID_ARGUMENT;
     if (params->ball == 2) return MLS_ERR_UNSUPPORTED;
+    // the grid's own points: `queries` is not read (only dtype, for the outputs)
+    if (own) queries = grid->g.view.pts;
   }
   const int stages = params->stages == 0 ? (MLS_STAGE_SEARCH | MLS_STAGE_FIT) : params->stages;
   if ((stages & MLS_STAGE_REFRESH) && !(stages & MLS_STAGE_SEARCH))
@@ -784,7 +791,13 @@ mls_status mls_project_geometry(const mls_grid *grid, const mls_params *params,
   mls_status st = prepare_queries(grid, params->k, k_list, queries, dtype, n_queries,
                                   query_offsets, workspace, workspace_bytes, sort, s, &qv, &L);
   if (st != MLS_OK || n_queries == 0) return st;
-  qv.slot_in = (params->slot_order & MLS_SLOT_QUERIES) ? 1 : 0;
+  qv.slot_in = (params->slot_order & (MLS_SLOT_QUERIES | MLS_SLOT_OWN_POINTS)) ? 1 : 0;
+  if (params->slot_order & MLS_SLOT_OWN_POINTS) {
+    // the sorted points {x, y, z, index} as the queries in sorted order
+    qv.q = grid->g.view.pts;
+    qv.in_f64 = 0;
+    qv.in_stride = 4;
+  }
   qv.slot_out = (params->slot_order & MLS_SLOT_OUTPUTS) ? 1 : 0;
   char *ws = (char *)workspace;
   int32_t *nbr = (int32_t *)(ws + L.nbr);

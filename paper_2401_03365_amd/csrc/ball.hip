@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64 * kBallWaves) void k_ball(GridView g, QueryView 
     const int64_t qi = __builtin_amdgcn_readfirstlane((int)query_of_slot(g, qv, p));
     const int64_t qo = out_index(qv, p, qi);  // where the results go
     double r[3];
-    load_query(qv, in_index(qv, p, qi), r);
+    load_slot_query(g, qv, p, qi, r);
     const bool lead = lane == 0;
     if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]))) {
       const double o[3] = {nanv, nanv, nanv};

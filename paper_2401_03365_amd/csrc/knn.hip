@@ -708,14 +708,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
       if (p < pend && ((todo >> lane) & 1)) {
         if (qv.aligned) qi = __float_as_int(g.pts[p].w);
         else qi = (int32_t)ordered_query(qv, p);
-        const int64_t qin = in_index(qv, p, qi);
-        if (qv.is_f64) {
-          const double *q = (const double *)qv.q + 3 * qin;
-          x = q[0]; y = q[1]; z = q[2];
-        } else {
-          const float *q = (const float *)qv.q + 3 * qin;
-          x = q[0]; y = q[1]; z = q[2];
-        }
+        double rq[3];
+        load_slot_query(g, qv, p, qi, rq);
+        x = rq[0]; y = rq[1]; z = rq[2];
         cl = qv.qcloud ? qv.qcloud[qi] : 0;
         qi = (int32_t)out_index(qv, p, qi);  // where the caller's lists go
       }
@@ -1010,13 +1005,7 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
   if (qv.aligned) qi = __float_as_int(g.pts[p].w);
   else qi = ordered_query(qv, p);
   double r[3];
-  if (qv.is_f64) {
-    const double *q = (const double *)qv.q + 3 * in_index(qv, p, qi);
-    r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
-  } else {
-    const float *q = (const float *)qv.q + 3 * in_index(qv, p, qi);
-    r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
-  }
+  load_slot_query(g, qv, p, qi, r);
   const double *an = anchor + 4 * p;
   const double bound = an[3];
   const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
@@ -1126,13 +1115,7 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
       else qi = ordered_query(qv, p);
       qi = __builtin_amdgcn_readfirstlane((int)qi);
       double r[3];
-      if (qv.is_f64) {
-        const double *q = (const double *)qv.q + 3 * in_index(qv, p, qi);
-        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
-      } else {
-        const float *q = (const float *)qv.q + 3 * in_index(qv, p, qi);
-        r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
-      }
+      load_slot_query(g, qv, p, qi, r);
       const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
       const double *an = anchor + 4 * p;
       const double bound = an[3];

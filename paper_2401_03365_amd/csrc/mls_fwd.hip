@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_forward(GridView g, QueryView qv
   const int64_t qi = query_of_slot(g, qv, p);
   const int64_t qo = out_index(qv, p, qi);  // where the results go
   double r[3];
-  load_query(qv, in_index(qv, p, qi), r);
+  load_slot_query(g, qv, p, qi, r);
   if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]))) {
     const double nanv = __longlong_as_double(0x7ff8000000000000ll);
     const double o[3] = {nanv, nanv, nanv};

@@ -204,6 +204,9 @@ struct QueryView {
   int32_t kstride;          // entries per query in the tile lists (k + search extra)
   int32_t slot_in;          // aligned queries given in the grid's sorted order (q[p])
   int32_t slot_out;         // results written in the grid's sorted order (out[p])
+  int32_t in_f64;           // query coordinates are doubles (else floats)
+  int32_t in_stride;        // elements from one query to the next: 3, or 4 when
+                            // the queries are the grid's own sorted points
 };
 
 // Index of slot p's query in the query array and of its results in the
@@ -214,6 +217,19 @@ __device__ __forceinline__ int64_t in_index(const QueryView &qv, int64_t p, int6
 }
 __device__ __forceinline__ int64_t out_index(const QueryView &qv, int64_t p, int64_t qi) {
   return qv.slot_out ? p : qi;
+}
+
+// The query of slot p (qi: its own index).
+__device__ __forceinline__ void load_slot_query(const GridView &g, const QueryView &qv,
+                                                int64_t p, int64_t qi, double r[3]) {
+  const int64_t i = in_index(qv, p, qi) * qv.in_stride;
+  if (qv.in_f64) {
+    const double *q = (const double *)qv.q + i;
+    r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+  } else {
+    const float *q = (const float *)qv.q + i;
+    r[0] = q[0]; r[1] = q[1]; r[2] = q[2];
+  }
 }
 
 // Query index of slot p < qv.n for queries that are not the grid's points:

@@ -14,7 +14,7 @@ from paper_2401_03365_amd import _abi, synth
 
 pytestmark = pytest.mark.gpu
 
-Q_, O_ = 1, 2
+Q_, O_, OWN = 1, 2, 4
 
 
 def api():
@@ -65,6 +65,24 @@ def test_slot_order_matches_caller_order(precision, moved):
     assert nan_eq(o4, o5[rows])
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_own_points_as_queries(dtype):
+    P = cloud(87)
+    h = synth.mean_nn_h(P[np.isfinite(P).all(1)])
+    Pt = torch.from_numpy(P).cuda()
+    g = api().Grid(Pt, h)
+    q = Pt.to(dtype)
+    rows = g.caller_rows()
+    for precision in ("fp32", "fp64"):
+        ref, rst = g.project(q, 24, precision)
+        junk = torch.full_like(q, 5.0)  # not read
+        o, st = g.project(junk, 24, precision, slot_order=OWN | O_)
+        assert o.dtype == dtype
+        assert nan_eq(o, ref[rows]) and torch.equal(st, rst[rows])
+        o, st = g.project(junk, 24, precision, slot_order=OWN)
+        assert nan_eq(o, ref) and torch.equal(st, rst)
+
+
 def test_iterated_passes_in_sorted_order():
     P = synth.heightfield(60000, sigma=1e-3, seed=83)
     h = synth.mean_nn_h(P)
@@ -88,7 +106,7 @@ def test_iterated_passes_in_sorted_order():
         return outs
 
     ref = passes([0, 0, 0])
-    got = passes([O_, Q_ | O_, Q_])
+    got = passes([OWN | O_, Q_ | O_, Q_])
     rows = g.caller_rows()
     for it, ((ro, rs), (go, gs)) in enumerate(zip(ref, got)):
         if it < 2:
@@ -120,7 +138,7 @@ def test_slot_order_argument_rules():
     qq = q.clone()
     for kw, code in ((dict(queries=q[:4000].contiguous(), slot_order=Q_), bad),  # not aligned
                      (dict(query_offsets=[0, 5000], slot_order=O_), bad),
-                     (dict(slot_order=4), bad),
+                     (dict(slot_order=8), bad),
                      (dict(queries=qq, out=qq, slot_order=Q_), bad),  # in place, orders differ
                      (dict(ball=2, slot_order=Q_ | O_), unsup)):
         kw = dict(kw)
