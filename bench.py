@@ -165,6 +165,9 @@ def parse():
                     help="queries per workload and pass in the accuracy table")
     ap.add_argument("--no-levin", action="store_true",
                     help="skip the 'levin' measurement (Levin's reference plane per fit)")
+    ap.add_argument("--gather-calibration-mb", type=int, default=0,
+                    help="only gather one 16-byte row from every 128-byte line of a table of "
+                         "this many MiB, in random order (counter calibration)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MB (3 times) and "
                          "print its bandwidth: the reference for the HBM traffic counters")
@@ -753,6 +756,28 @@ def main():
             log("copy %d MiB: %.3f ms, %.1f GB/s (read + write)" %
                 (args.copy_calibration_mb, e0.elapsed_time(e1), 2 * nbytes / e0.elapsed_time(e1) / 1e6))
         print(json.dumps({"copy_bytes": nbytes, "ms": e0.elapsed_time(e1)}), flush=True)
+        return
+
+    if args.gather_calibration_mb:
+        # rows of 16 bytes (float4, as the fit gathers its neighbours), one
+        # from each 128-byte line of the table, in random order: every row
+        # read touches a line no other read touches
+        nbytes = args.gather_calibration_mb << 20
+        table = torch.ones((nbytes // 16, 4), dtype=torch.float32, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        idx = torch.randperm(nbytes // 128, device="cuda", generator=g) * 8
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            e0.record()
+            out = table.index_select(0, idx)
+            e1.record()
+            torch.cuda.synchronize()
+            log("gather of %d rows of 16 B from a %d MiB table: %.3f ms" %
+                (idx.numel(), args.gather_calibration_mb, e0.elapsed_time(e1)))
+        del out
+        print(json.dumps({"rows": idx.numel(), "row_bytes": 16, "line_bytes": 128,
+                          "index_bytes": 8, "ms": e0.elapsed_time(e1)}), flush=True)
         return
 
     t = time.perf_counter()
