@@ -13,13 +13,15 @@
 // usually fall in the same cell. The grid indexes cells at several levels
 // (edges c, 2c, 4c, 8c: a coarse cell is a contiguous Morton range of the
 // sorted points). For each query the wave
-// uses the 3x3x3 block of cells around the query's cell at a level chosen so
-// that the block both holds the k nearest and fits the candidate slots (the
-// level follows the previous query's k-th distance, so it adapts to the
-// local density). The block's candidates -- cell lookups, their prefix sum
-// and the candidate coordinates -- are gathered once into registers (lanes x
-// slots) and reused by every following query of the chunk in the same cell;
-// per query only the FP64 keys and the selection remain.
+// uses the 3x3x3 or 5x5x5 block of cells around the query's cell at a level
+// chosen so that the block holds the k nearest (the level follows the
+// previous query's k-th distance, so it adapts to the local density). The
+// block's cells are staged nearest first -- cell lookups and their prefix
+// sum in LDS -- and its first 256 candidates (coordinates, positions,
+// indices) are gathered once into registers (lanes x slots) and reused by
+// every following query of the chunk in the same block: per query the FP64
+// keys and the selection of those, then the rest of a larger block 64
+// candidates at a time, each entering only below the k-th pair so far.
 //
 // Certification: the distance beta from the query to the boundary of the
 // visited box (faces beyond the cloud's grid count as infinitely far; a
@@ -491,17 +493,44 @@ __device__ __forceinline__ int32_t stage_cells(const GridView &g, int cloud, con
   return stage_ranges(lookup_if(g, cloud, cd, has, cx, cy, cz, level), make_int2(0, 0), L, lane);
 }
 
-// The (2 half + 1)^3 block of level-`level` cells around cell cl (half 1 or 2).
+// Cell offsets of a (2 half + 1)^3 block in order of their squared distance
+// from the centre cell (nearest first), so that the first candidates of a
+// staged block are those of the cells nearest the query.
+struct CellOrder {
+  int8_t d[125][3];
+};
+constexpr CellOrder make_cell_order(int half) {
+  CellOrder o{};
+  int n = 0;
+  for (int r2 = 0; r2 <= 3 * half * half; ++r2)
+    for (int z = -half; z <= half; ++z)
+      for (int y = -half; y <= half; ++y)
+        for (int x = -half; x <= half; ++x)
+          if (x * x + y * y + z * z == r2) {
+            o.d[n][0] = (int8_t)x;
+            o.d[n][1] = (int8_t)y;
+            o.d[n][2] = (int8_t)z;
+            ++n;
+          }
+  return o;
+}
+__constant__ CellOrder kCellOrder3 = make_cell_order(1);
+__constant__ CellOrder kCellOrder5 = make_cell_order(2);
+
+// The (2 half + 1)^3 block of level-`level` cells around cell cl (half 1 or
+// 2), nearest cells first.
 __device__ __forceinline__ int32_t stage_block(const GridView &g, int cloud, const CloudDev &cd,
                                                const int32_t cl[3], int half, int level,
                                                WaveLds &L, int lane) {
   const int w = 2 * half + 1;
   const int n = w * w * w;
+  const CellOrder &ord = half == 1 ? kCellOrder3 : kCellOrder5;
   int2 ab[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int t = lane + 64 * e;
-    const int dx = t % w - half, dy = (t / w) % w - half, dz = t / (w * w) - half;
+    const int tt = t < n ? t : 0;
+    const int dx = ord.d[tt][0], dy = ord.d[tt][1], dz = ord.d[tt][2];
     ab[e] = lookup_if(g, cloud, cd, t < n, cl[0] + dx, cl[1] + dy, cl[2] + dz, level);
   }
   return stage_ranges(ab[0], ab[1], L, lane);
@@ -682,7 +711,6 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
     int32_t cc0[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     int ccloud = -1, copt = -1;
     int32_t ncand = -1;
-    bool cached = false;  // candidate slots hold the staged block
     double rho_est = 0.0;  // k-th distance of the previous query of the chunk
     float cx[kSlots], cy[kSlots], cz[kSlots];
     Slots s;
@@ -783,19 +811,19 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
               ccloud = cloud;
               copt = opt;
               ncand = stage_block(g, cloud, cd, cl, half, lt, L, lane);
-              cached = ncand <= kNew;
-              if (cached) {
+              // the slots cache the first kNew candidates (the nearest cells'):
+              // all of them, or the part a larger block's queries keep and
+              // complete from the rest of the block per query
 #pragma unroll
-                for (int sl = 1; sl < kSlots; ++sl) {
-                  if ((sl - 1) * 64 < ncand) {
-                    const int32_t ci = (sl - 1) * 64 + lane;
-                    int32_t pos = ci < ncand ? cand_pos(L, ci) : 0;
-                    pos = (pos >= 0 && (int64_t)pos < g.n_points) ? pos : 0;
-                    const float4 P = g.pts[pos];
-                    cx[sl] = P.x; cy[sl] = P.y; cz[sl] = P.z;
-                    s.pos[sl] = pos;
-                    s.idx[sl] = __float_as_int(P.w);
-                  }
+              for (int sl = 1; sl < kSlots; ++sl) {
+                if ((sl - 1) * 64 < ncand) {
+                  const int32_t ci = (sl - 1) * 64 + lane;
+                  int32_t pos = ci < ncand ? cand_pos(L, ci) : 0;
+                  pos = (pos >= 0 && (int64_t)pos < g.n_points) ? pos : 0;
+                  const float4 P = g.pts[pos];
+                  cx[sl] = P.x; cy[sl] = P.y; cz[sl] = P.z;
+                  s.pos[sl] = pos;
+                  s.idx[sl] = __float_as_int(P.w);
                 }
               }
             }
@@ -811,7 +839,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
             uint64_t kmax = kEmptyKey;
             int32_t imax = 0x7fffffff;
             bool exact_max = false;
-            if (cached) {
+            {
+              const bool partial = ncand > kNew;
 #pragma unroll
               for (int sl = 1; sl < kSlots; ++sl) {
                 if ((sl - 1) * 64 < ncand) {
@@ -838,32 +867,37 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
               uint32_t total;
               const int bstar = select_topk(s, k, scale, L, lane, keep, &total);
               ntop = compact(s, keep, L, lane);
-              if (bstar >= 0 && bstar < 255 && !inf) {
+              if (!partial && bstar >= 0 && bstar < 255 && !inf) {
                 kmax = dbits((double)(bstar + 1) / scale);  // upper bound of the k-th key
               } else {
                 top_max(s, ntop, lane, kmax, imax);
                 exact_max = true;
               }
-            } else {
-              // more candidates than slots: batches from the staged ranges
-              ntop = 0;
+              // the rest of a large block, 64 candidates at a time, each
+              // entering only below the current k-th pair
+              for (int32_t b0 = kNew; b0 < ncand; b0 += 64) {
+                const int32_t ci = b0 + lane;
+                const bool present = ci < ncand;
+                const int32_t pos = present ? cand_pos(L, ci) : 0;
+                const bool inb = pos >= 0 && (int64_t)pos < g.n_points;
+                float4 P = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (present && inb) P = g.pts[pos];
+                const uint64_t key =
+                    dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]));
+                const int32_t idx = __float_as_int(P.w);
+                const bool take = present && inb && (ntop < k || pair_lt(key, idx, kmax, imax));
+                if (__ballot(take) == 0ull) continue;
+                Slots t;
+                t.key[0] = s.key[0]; t.pos[0] = s.pos[0]; t.idx[0] = s.idx[0];
+                t.key[1] = take ? key : kEmptyKey; t.pos[1] = pos; t.idx[1] = idx;
 #pragma unroll
-              for (int i = 0; i < kSlots; ++i) s.key[i] = kEmptyKey;
-              for (int32_t b0 = 0; b0 < ncand; b0 += kNew) {
-#pragma unroll
-                for (int sl = 1; sl < kSlots; ++sl) {
-                  const int32_t ci = b0 + (sl - 1) * 64 + lane;
-                  const bool present = ci < ncand;
-                  const int32_t pos = present ? cand_pos(L, ci) : 0;
-                  const bool inb = pos >= 0 && (int64_t)pos < g.n_points;
-                  put_candidate(g, inb ? pos : 0, present && inb, r, ntop, k, kmax, imax, s, sl);
+                for (int i = 2; i < kSlots; ++i) {
+                  t.key[i] = kEmptyKey; t.pos[i] = 0; t.idx[i] = 0x7fffffff;
                 }
-                bool any = false;
-#pragma unroll
-                for (int sl = 1; sl < kSlots; ++sl) any |= __ballot(s.key[sl] != kEmptyKey) != 0ull;
-                if (any) merge_general(s, ntop, k, kmax, imax, L, lane);
+                merge_general(t, ntop, k, kmax, imax, L, lane);
+                s.key[0] = t.key[0]; s.pos[0] = t.pos[0]; s.idx[0] = t.idx[0];
               }
-              if (ntop == k) exact_max = true;
+              if (partial) exact_max = ntop == k;
             }
             const bool done = ntop == k ? (inf || bitsd(kmax) < bound) : inf;
             if (done) {
@@ -882,7 +916,6 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
           ntop = search_general(g, cloud, cd, r, c0, k, s, L, lane);
           cc0[0] = INT32_MIN;  // the general path reused the candidate slots
           copt = -1;
-          cached = false;
         }
       }
 
