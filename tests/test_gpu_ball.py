@@ -11,8 +11,11 @@ max |out - oracle| <= 1e-10 h with each point's error first divided by
 max(1, 1e-6 / p), p the oracle's smallest relative Cholesky pivot of the 6x6
 fit (small balls of a handful of points give fits with condition numbers up
 to ~1e9 just above the 1e-12 pivot rule, and the rounding error of a solve
-grows with the condition number); FP32-moment path RMS <= 1e-5 h over the
-points with p >= 1e-4, the others (at most 5 %) finite."""
+grows with the condition number); FP32-moment path, every point within
+max(1e-4 h, 10 eps32 / min(p, gap) h), gap the oracle plane's relative
+eigengap (the FP32 moments perturb the fit's solve and the plane's normal by
+about eps32 / p and eps32 / gap), and RMS <= 1e-5 h over the points with
+p >= 1e-4 (all but at most 5 %)."""
 import numpy as np
 import pytest
 import torch
@@ -24,6 +27,8 @@ pytestmark = pytest.mark.gpu
 
 FP64_MAX_H = 1e-10
 FP32_RMS_H = 1e-5
+FP32_MAX_H = 1e-4
+EPS32 = 2.0 ** -24
 
 
 def api():
@@ -72,11 +77,23 @@ def check(orc, P64, Q, k, h, out, st, precision, radius_h, iters=0, uncapped=Fal
         # pivot is below 1e-4: the output is as uncertain as the fit is ill
         # conditioned, so those points (a few per cent of small balls) are
         # only required to be finite
+        # FP32 moments (relative rounding ~1e-7): the output moves by about
+        # eps32 / p with p the fit's smallest relative Cholesky pivot (the
+        # solve's conditioning) and by about eps32 / gap with gap the plane's
+        # relative eigengap (first-order eigenvector perturbation), so each
+        # point's bar is the larger of 1e-4 h and 10 eps32 / min(p, gap) h
+        # (measured on these clouds: at most 4.6 eps32 / min(p, gap));
+        # small balls give fits with p below 1e-4 on a few per cent of the
+        # points, which are left out of the RMS
+        gap = np.nan_to_num(relative_gap(dg[:, 3:6]), nan=1.0)
+        bar = np.maximum(FP32_MAX_H, 10.0 * EPS32 / np.maximum(np.minimum(piv, gap), 1e-300))
+        err = np.linalg.norm(diff, axis=1) / h
+        over = ok & ~(err <= bar)
+        assert not over.any(), (np.flatnonzero(over)[:5], err[over][:5], bar[over][:5])
         well = piv >= 1e-4
-        assert np.all(np.isfinite(out[ok]))
         assert (ok & ~well).sum() <= 0.05 * ok.sum()
-        err = np.linalg.norm(diff, axis=1)[ok & well] / h
-        assert np.sqrt((err ** 2).mean()) <= FP32_RMS_H, np.sqrt((err ** 2).mean())
+        rms = np.sqrt((err[ok & well] ** 2).mean()) if (ok & well).any() else 0.0
+        assert rms <= FP32_RMS_H, rms
     return ref_st
 
 
