@@ -17,7 +17,7 @@
 // chosen so that the block holds the k nearest (the level follows the
 // previous query's k-th distance, so it adapts to the local density). The
 // block's cells are staged nearest first -- cell lookups and their prefix
-// sum in LDS -- and its first 256 candidates (coordinates, positions,
+// sum in LDS -- and its first 192 candidates (coordinates, positions,
 // indices) are gathered once into registers (lanes x slots) and reused by
 // every following query of the chunk in the same block: per query the FP64
 // keys and the selection of those, then the rest of a larger block 64
@@ -31,7 +31,7 @@
 // general path: shells of growing Chebyshev radius L around the query's
 // level-0 cell, then an exhaustive scan of the cloud beyond kMaxRing.
 //
-// Selection (k of up to 320 pairs): keys are bucketed by a monotone map
+// Selection (k of up to 256 pairs): keys are bucketed by a monotone map
 // b = floor(key * scale) into 256 bins; an LDS histogram and its prefix sum
 // give the bin b* holding the k-th pair; bins below b* are kept and inside b*
 // the needed number of smallest pairs is found by ranking (small bins) or by
@@ -42,7 +42,7 @@ namespace mls {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kSlots = 5;                 // slot 0 = running top-k, 1..4 = candidates
+constexpr int kSlots = 4;                 // slot 0 = running top-k, 1..3 = candidates
 constexpr int kNew = (kSlots - 1) * 64;   // candidates per batch
 constexpr int kMaxRing = 12;
 constexpr int kChunk = 64;                // consecutive queries per wave task
@@ -54,9 +54,10 @@ struct alignas(16) ChunkQueries {
   int32_t cloud[kChunk];
 };
 
-// List entries of up to 16 consecutive queries (entry j of the g-th query of
-// the group at [g][j]), flushed to the tiles as 64-byte segments per entry.
-constexpr int kListGroup = 16;
+// List entries of up to 8 consecutive queries (entry j of the g-th query of
+// the group at [g][j]), flushed to the tiles as 32-byte segments per entry
+// (a smaller group leaves the LDS room for 5 blocks per CU).
+constexpr int kListGroup = 8;
 struct alignas(16) ListGroup {
   int32_t e[kListGroup][64];
 };
@@ -675,14 +676,14 @@ __device__ int search_general(const GridView &g, int cloud, const CloudDev &cd, 
 // caller lists) or kAny; each compiled without the branches of the others.
 constexpr int kPlain = 0, kExtra = 1, kFlagged = 2, kAny = 3;
 template <int kMode>
-__global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, QueryView qv, int32_t k,
-                                                            int32_t kfit, double support_r_h,
-                                                            int32_t *__restrict__ nbr,
-                                                            uint8_t *__restrict__ support,
-                                                            double *__restrict__ anchor,
-                                                            const uint8_t *__restrict__ slot_flag,
-                                                            int32_t *__restrict__ out_nbr,
-                                                            double *__restrict__ out_keys) {
+// The full-search variants run 5 waves per SIMD (96 VGPRs, a few spills
+// outside the hot loops): the extra wave hides more of the staging's global
+// round trips than the registers would save; the others keep 4.
+__global__ __launch_bounds__(64 * kWavesPerBlock, (kMode == kFlagged || kMode == kAny) ? 4 : 5)
+void k_knn(GridView g, QueryView qv, int32_t k, int32_t kfit, double support_r_h,
+           int32_t *__restrict__ nbr, uint8_t *__restrict__ support, double *__restrict__ anchor,
+           const uint8_t *__restrict__ slot_flag, int32_t *__restrict__ out_nbr,
+           double *__restrict__ out_keys) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ ChunkQueries chq[kWavesPerBlock];
   __shared__ ListGroup lgr[kWavesPerBlock];
@@ -944,7 +945,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 4) void k_knn(GridView g, Quer
         else nbr[(p >> 6) * 64 * k + lane * 64 + (p & 63)] = e;
       }
       if (grouped && ((j & (kListGroup - 1)) == kListGroup - 1 || p == pend - 1)) {
-        // the group's row segments, 16 entries (64 B) per list row; rows of
+        // the group's row segments, 8 entries (32 B) per list row; rows of
         // slots past the last query hold -1
         wave_sync();
         const int g0 = j & ~(kListGroup - 1), gn = (j & (kListGroup - 1)) + 1;
