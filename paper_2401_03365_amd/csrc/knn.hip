@@ -135,6 +135,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
   return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -1058,18 +1065,44 @@ __global__ __launch_bounds__(256) void k_knn_refresh_lane(GridView g, QueryView 
   }
   int m = 0;
   bool valid = true;
-  for (int j = 0; j < k; ++j) {
-    const int32_t pos = row[j * 64];
-    const bool have = pos >= 0 && (int64_t)pos < g.n_points;
-    const float4 P = g.pts[have ? pos : 0];
-    const uint64_t key = dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]));
-    const int32_t idx = __float_as_int(P.w);
-    if (j < kfit) {
-      valid = valid && have;
-      m += (have && bitsd(key) <= rad2) ? 1 : 0;
-      ents_insert<true>(hi, key, idx, j, pos);
-    } else if (have) {
-      ents_insert<false>(lo, key, idx, j, pos);
+  // positions and points of 4 entries are loaded ahead of their use
+  constexpr int kAhead = 4;
+  int32_t pq[kAhead];
+  float4 Pq[kAhead];
+#pragma unroll
+  for (int a = 0; a < kAhead; ++a) pq[a] = a < k ? row[a * 64] : -1;
+#pragma unroll
+  for (int a = 0; a < kAhead; ++a) {
+    const bool hv = pq[a] >= 0 && (int64_t)pq[a] < g.n_points;
+    Pq[a] = g.pts[hv ? pq[a] : 0];
+  }
+  for (int j0 = 0; j0 < k; j0 += kAhead) {
+    int32_t pn[kAhead];
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a)
+      pn[a] = j0 + kAhead + a < k ? row[(j0 + kAhead + a) * 64] : -1;
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a) {
+      const int j = j0 + a;
+      if (j >= k) break;
+      const int32_t pos = pq[a];
+      const bool have = pos >= 0 && (int64_t)pos < g.n_points;
+      const float4 P = Pq[a];
+      const uint64_t key = dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]));
+      const int32_t idx = __float_as_int(P.w);
+      if (j < kfit) {
+        valid = valid && have;
+        m += (have && bitsd(key) <= rad2) ? 1 : 0;
+        ents_insert<true>(hi, key, idx, j, pos);
+      } else if (have) {
+        ents_insert<false>(lo, key, idx, j, pos);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a) {
+      pq[a] = pn[a];
+      const bool hv = pq[a] >= 0 && (int64_t)pq[a] < g.n_points;
+      Pq[a] = g.pts[hv ? pq[a] : 0];
     }
   }
   // pairs out of order: lo[i] < hi[i] holds for i < s (both sides monotone)
@@ -1142,16 +1175,47 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
       todo = __ballot(p0 + lane < pend && slot_flag[p0 + lane] == 2);
       if (todo == 0) continue;
     }
-    for (int64_t p = p0; p < pend; ++p) {
-      if (!((todo >> (p - p0)) & 1)) continue;
-      int64_t qi;
-      if (qv.aligned) qi = __float_as_int(g.pts[p].w);
-      else qi = ordered_query(qv, p);
-      qi = __builtin_amdgcn_readfirstlane((int)qi);
-      double r[3];
-      load_slot_query(g, qv, p, qi, r);
+    // lane j holds slot p0 + j's query index, query and anchor (one round
+    // trip for the chunk; each slot then reads them across the lanes)
+    int32_t lqi = 0;
+    double lr[3] = {0.0, 0.0, 0.0}, lan[4] = {0.0, 0.0, 0.0, -1.0};
+    if (p0 + lane < pend && ((todo >> lane) & 1)) {
+      const int64_t pl = p0 + lane;
+      lqi = qv.aligned ? __float_as_int(g.pts[pl].w) : (int32_t)ordered_query(qv, pl);
+      load_slot_query(g, qv, pl, lqi, lr);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) lan[c] = anchor[4 * pl + c];
+    }
+    // the list row of the next slot to refresh, and its points, are loaded
+    // while the current one is ranked
+    auto next_slot = [&](int64_t from) {
+      const uint64_t rest = from - p0 < 64 ? todo & (~0ull << (from - p0)) : 0ull;
+      return rest ? p0 + (int64_t)__builtin_ctzll(rest) : pend;
+    };
+    int64_t pn = next_slot(p0);
+    int32_t pos_n = -1;
+    float4 P_n = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (pn < pend) {
+      pos_n = lane < k ? nbr[(pn >> 6) * 64 * k + lane * 64 + (pn & 63)] : -1;
+      const bool hv = pos_n >= 0 && (int64_t)pos_n < g.n_points;
+      P_n = g.pts[hv ? pos_n : 0];
+    }
+    for (int64_t p = pn; p < pend; p = pn) {
+      const int32_t pos_c = pos_n;
+      const float4 P_c = P_n;
+      pn = next_slot(p + 1);
+      if (pn < pend) {
+        pos_n = lane < k ? nbr[(pn >> 6) * 64 * k + lane * 64 + (pn & 63)] : -1;
+        const bool hv = pos_n >= 0 && (int64_t)pos_n < g.n_points;
+        P_n = g.pts[hv ? pos_n : 0];
+      }
+      const int jl = (int)(p - p0);
+      const int64_t qi = __builtin_amdgcn_readlane(lqi, jl);
+      const double r[3] = {readlane_f64(lr[0], jl), readlane_f64(lr[1], jl),
+                           readlane_f64(lr[2], jl)};
       const bool finite = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]);
-      const double *an = anchor + 4 * p;
+      const double an[4] = {readlane_f64(lan[0], jl), readlane_f64(lan[1], jl),
+                            readlane_f64(lan[2], jl), readlane_f64(lan[3], jl)};
       const double bound = an[3];
       int32_t *row = nbr + (p >> 6) * 64 * k + (p & 63);
       if (!finite) {
@@ -1166,9 +1230,9 @@ __global__ __launch_bounds__(256) void k_knn_refresh(GridView g, QueryView qv, i
         }
         continue;
       }
-      int32_t pos = lane < k ? row[lane * 64] : -1;
+      const int32_t pos = pos_c;
       const bool have = pos >= 0 && (int64_t)pos < g.n_points;
-      const float4 P = g.pts[have ? pos : 0];
+      const float4 P = P_c;
       uint64_t mk = have ? dbits(canon_key((double)P.x, (double)P.y, (double)P.z, r[0], r[1], r[2]))
                          : kEmptyKey;
       int32_t mi = have ? __float_as_int(P.w) : 0x7fffffff;
