@@ -533,13 +533,40 @@ __device__ __forceinline__ int32_t stage_block(const GridView &g, int cloud, con
   const int w = 2 * half + 1;
   const int n = w * w * w;
   const CellOrder &ord = half == 1 ? kCellOrder3 : kCellOrder5;
+  // both lanes' cells probe their home slots together (two loads in flight),
+  // then the rare collisions walk on
   int2 ab[2];
+  uint64_t key[2], slot[2];
+  bool need[2];
+  uint4 e4[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int t = lane + 64 * e;
     const int tt = t < n ? t : 0;
-    const int dx = ord.d[tt][0], dy = ord.d[tt][1], dz = ord.d[tt][2];
-    ab[e] = lookup_if(g, cloud, cd, t < n, cl[0] + dx, cl[1] + dy, cl[2] + dz, level);
+    const int32_t cx = cl[0] + ord.d[tt][0], cy = cl[1] + ord.d[tt][1], cz = cl[2] + ord.d[tt][2];
+    need[e] = t < n && cx >= 0 && cy >= 0 && cz >= 0 && cx <= ((cd.dims[0] - 1) >> level) &&
+              cy <= ((cd.dims[1] - 1) >> level) && cz <= ((cd.dims[2] - 1) >> level);
+    key[e] = level_cell_key(cloud, cx, cy, cz, g.morton_bits, level);
+    slot[e] = hash_slot(key[e], g.hash_shift);
+    ab[e] = make_int2(0, 0);
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) e4[e] = need[e] ? g.table[slot[e]] : make_uint4(~0u, ~0u, 0u, 0u);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    for (uint64_t probe = 0; need[e] && probe <= g.hash_mask; ++probe) {
+      const uint64_t kk = (uint64_t)e4[e].x | ((uint64_t)e4[e].y << 32);
+      if (kk == key[e]) {
+        const int64_t st = (int64_t)e4[e].z, en = (int64_t)e4[e].w;
+        if (en >= st && en <= g.n_points) ab[e] = make_int2((int)st, (int)(en - st));
+        need[e] = false;
+      } else if (kk == kEmptyKey) {
+        need[e] = false;
+      } else {
+        slot[e] = (slot[e] + 1) & g.hash_mask;
+        e4[e] = g.table[slot[e]];
+      }
+    }
   }
   return stage_ranges(ab[0], ab[1], L, lane);
 }
