@@ -763,12 +763,15 @@ void k_knn(GridView g, QueryView qv, int32_t k, int32_t kfit, double support_r_h
       todo = __ballot(p0 + lane < pend && slot_flag[p0 + lane] != 0);
       if (todo == 0) continue;
     }
+    // for the slots a refresh left: lane j holds slot p0 + j's hint
+    double hint_l = 0.0;
     {
       // lane j loads query slot p0 + j (one round trip for the chunk)
       const int64_t p = p0 + lane;
       int32_t qi = 0, cl = 0;
       double x = 0.0, y = 0.0, z = 0.0;
       if (p < pend && ((todo >> lane) & 1)) {
+        if (slot_flag) hint_l = anchor[4 * p + 3];
         if (qv.aligned) qi = __float_as_int(g.pts[p].w);
         else qi = (int32_t)ordered_query(qv, p);
         double rq[3];
@@ -790,7 +793,7 @@ void k_knn(GridView g, QueryView qv, int32_t k, int32_t kfit, double support_r_h
         // entry from the moved query (its k nearest lie within it); that
         // bound is loose, so the block targets the smaller of it and the
         // previous query's k-th distance
-        const double hint = anchor[4 * p + 3];
+        const double hint = readlane_f64(hint_l, (int)(p - p0));
         if (hint > 0.0 && isfinite(hint))
           rho_est = rho_est > 0.0 ? fmin(rho_est, sqrt(hint)) : sqrt(hint);
       }
