@@ -118,23 +118,28 @@ __device__ __forceinline__ void pass2_adjoint_sums(const GridView &g, const int3
 // LDS keyed by sorted position (keys only inserted during the phase; probe
 // step kStride), flushed to the global buffer with one atomic per component and
 // distinct point. The 256 queries of a block are consecutive in Morton order
-// and share most neighbours (about 700 distinct points for 12k list entries
+// and share most neighbours (about 800 distinct points for 12k list entries
 // at k = 48), so the table removes most global atomics. An entry that finds
-// no slot within kProbes goes straight to global memory.
-template <typename T>
+// no slot within kProbes goes straight to global memory. The table sums in
+// FP64 for both paths: on gfx950 the LDS FP32 add (ds_add_f32) is several
+// times slower than the FP64 one, and the FP32-moment kernel's three adds per
+// list entry took 4 ms of a 10 ms adjoint at 10M points, k = 48; FP64 slots
+// are larger, so that kernel's table has fewer of them (kSlots: 1,408 and
+// 39 KB, so 4 blocks still fit a CU's LDS; 2,048 for the FP64 kernel).
+template <bool kF32>
 struct ScatterTable {
-  static constexpr int kLog2 = 11;
-  static constexpr int kSlots = 1 << kLog2;
+  using T = Real<kF32>;
+  static constexpr uint32_t kSlots = kF32 ? 1408 : 2048;
   static constexpr int kProbes = 32;
-  static constexpr uint32_t kStride = 523;  // odd: visits every slot
+  static constexpr uint32_t kStride = 523;  // coprime with kSlots: visits every slot
   int32_t *key;  // kSlots, -1 = empty
-  T *val;        // 3 x kSlots
+  double *val;   // 3 x kSlots
   T *gp;         // global, sorted order, xyz interleaved
 
   __device__ __forceinline__ void add(int32_t pos, T v0, T v1, T v2) const {
-    // positions of a block's neighbours come in runs: the low bits spread a
-    // run over distinct slots, and a collision jumps away from the run
-    uint32_t s = (uint32_t)pos & (kSlots - 1);
+    // positions of a block's neighbours come in runs: consecutive positions
+    // take consecutive slots, and a collision jumps away from the run
+    uint32_t s = (uint32_t)pos % kSlots;
 #pragma unroll 1
     for (int probe = 0; probe < kProbes; ++probe) {
       int32_t cur = __hip_atomic_load(key + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -146,14 +151,16 @@ struct ScatterTable {
         if (cur == -1) cur = pos;
       }
       if (cur == pos) {
-        __hip_atomic_fetch_add(val + s, v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_add(val + kSlots + s, v1, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(val + s, (double)v0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_add(val + 2 * kSlots + s, v2, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(val + kSlots + s, (double)v1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(val + 2 * kSlots + s, (double)v2, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
         return;
       }
-      s = (s + kStride) & (kSlots - 1);
+      s += kStride;
+      if (s >= kSlots) s -= kSlots;
     }
     T *dst = gp + 3 * (int64_t)pos;
     unsafeAtomicAdd(dst + 0, v0);
@@ -168,7 +175,7 @@ __device__ __forceinline__ void final_adjoint(const GridView &g, const int32_t *
                                               const Real<kF32> a[6], const Real<kF32> bb[6],
                                               Real<kF32> Sb0, const Real<kF32> Sb1[3],
                                               const Real<kF32> Sb2[6], Real<kF32> ih,
-                                              const ScatterTable<Real<kF32>> &tab, double D[3]) {
+                                              const ScatterTable<kF32> &tab, double D[3]) {
   using T = Real<kF32>;
   Acc<kF32, 3> A;
   A.zero();
@@ -243,7 +250,7 @@ __device__ __forceinline__ void backward_one(const GridView &g, const QueryView 
                                              const int32_t *__restrict__ nbr,
                                              const void *__restrict__ grad_out,
                                              void *__restrict__ grad_q,
-                                             const ScatterTable<Real<kF32>> &tab, int64_t p) {
+                                             const ScatterTable<kF32> &tab, int64_t p) {
   using T = Real<kF32>;
   const int64_t qi = query_of_slot(g, qv, p);
   double r[3], gb[3];
@@ -371,9 +378,10 @@ __device__ __forceinline__ void backward_one(const GridView &g, const QueryView 
   store_vec(grad_q, qv.is_f64, qi, rb);
 }
 
-// FP32 moments: 4 waves per SIMD (the LDS table allows 5 blocks per CU; the
-// neighbour loops are latency-bound and gain more from the waves than they
-// lose to the spills of the FP64 solve state); FP64: the 56 KB table allows 2.
+// FP32 moments: 4 waves per SIMD (the 39 KB LDS table allows 4 blocks per
+// CU; the neighbour loops are latency-bound and gain more from the waves than
+// they lose to the spills of the FP64 solve state); FP64: the 56 KB table
+// allows 2.
 template <bool kF32>
 __global__ __launch_bounds__(kBlock, kF32 ? 4 : 2) void k_mls_backward(GridView g, QueryView qv, int32_t k,
                                                          double support_radius_h,
@@ -383,14 +391,14 @@ __global__ __launch_bounds__(kBlock, kF32 ? 4 : 2) void k_mls_backward(GridView 
                                                          void *__restrict__ grad_q,
                                                          Real<kF32> *__restrict__ gp) {
   using T = Real<kF32>;
-  using Tab = ScatterTable<T>;
+  using Tab = ScatterTable<kF32>;
   __shared__ int32_t skey[Tab::kSlots];
-  __shared__ T sval[3 * Tab::kSlots];
-  for (int i = threadIdx.x; i < Tab::kSlots; i += kBlock) {
+  __shared__ double sval[3 * Tab::kSlots];
+  for (int i = threadIdx.x; i < (int)Tab::kSlots; i += kBlock) {
     skey[i] = -1;
-    sval[i] = (T)0;
-    sval[Tab::kSlots + i] = (T)0;
-    sval[2 * Tab::kSlots + i] = (T)0;
+    sval[i] = 0.0;
+    sval[Tab::kSlots + i] = 0.0;
+    sval[2 * Tab::kSlots + i] = 0.0;
   }
   __syncthreads();
   const Tab tab{skey, sval, gp};
@@ -398,13 +406,13 @@ __global__ __launch_bounds__(kBlock, kF32 ? 4 : 2) void k_mls_backward(GridView 
   if (p < qv.n)
     backward_one<kF32>(g, qv, k, support_radius_h, min_support, nbr, grad_out, grad_q, tab, p);
   __syncthreads();
-  for (int i = threadIdx.x; i < Tab::kSlots; i += kBlock) {
+  for (int i = threadIdx.x; i < (int)Tab::kSlots; i += kBlock) {
     const int32_t pos = skey[i];
     if (pos >= 0) {
       T *dst = gp + 3 * (int64_t)pos;
-      unsafeAtomicAdd(dst + 0, sval[i]);
-      unsafeAtomicAdd(dst + 1, sval[Tab::kSlots + i]);
-      unsafeAtomicAdd(dst + 2, sval[2 * Tab::kSlots + i]);
+      unsafeAtomicAdd(dst + 0, (T)sval[i]);
+      unsafeAtomicAdd(dst + 1, (T)sval[Tab::kSlots + i]);
+      unsafeAtomicAdd(dst + 2, (T)sval[2 * Tab::kSlots + i]);
     }
   }
 }
