@@ -126,12 +126,17 @@ __device__ __forceinline__ void pass2_adjoint_sums(const GridView &g, const int3
 // list entry took 4 ms of a 10 ms adjoint at 10M points, k = 48; FP64 slots
 // are larger, so that kernel's table has fewer of them (kSlots: 1,408 and
 // 39 KB, so 4 blocks still fit a CU's LDS; 2,048 for the FP64 kernel).
+constexpr uint32_t gcd_u32(uint32_t a, uint32_t b) { return b ? gcd_u32(b, a % b) : a; }
+
 template <bool kF32>
 struct ScatterTable {
   using T = Real<kF32>;
   static constexpr uint32_t kSlots = kF32 ? 1408 : 2048;
   static constexpr int kProbes = 32;
   static constexpr uint32_t kStride = 523;  // coprime with kSlots: visits every slot
+  static_assert(gcd_u32(kStride, kSlots) == 1, "the probe must reach every slot");
+  static_assert(!kF32 || 4 * kSlots * (sizeof(int32_t) + 3 * sizeof(double)) <= 160 * 1024,
+                "four FP32-moment blocks must fit a CU's LDS");
   int32_t *key;  // kSlots, -1 = empty
   double *val;   // 3 x kSlots
   T *gp;         // global, sorted order, xyz interleaved
