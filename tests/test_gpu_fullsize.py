@@ -11,7 +11,8 @@ brute-force kNN over the whole cloud:
       Levin's plane (both paths), and 40,000,000
       upsampling queries (positions, lists, geometry);
   bumped sphere 2,000,000, k = 32, FP32 forward and the adjoint (1,000
-      queries against central finite differences);
+      queries against central finite differences, by themselves and as the
+      only nonzero output gradients of the whole-cloud call);
   batch of 256 clouds, ~30M points, k = 32, FP32.
 
 Bars as in the small-size tests: neighbour lists and statuses bit for bit,
@@ -222,6 +223,18 @@ def test_bumped_sphere_2m_forward_and_adjoint(orc):
     # the full call's query gradients agree with the sampled call's
     gfull = gq_full[idx_t].cpu().numpy().astype(np.float64)[keep]
     assert np.linalg.norm(gfull - gq) <= 1e-5 * np.linalg.norm(gq)
+    # the full aligned call with the output gradient only at the checked
+    # queries: its point gradients are summed in the block tables of
+    # Morton-consecutive queries (the timed path) and must meet the finite
+    # differences too
+    gm = torch.zeros_like(gout)
+    kidx = idx_t[torch.from_numpy(keep).cuda()]
+    gm[kidx] = torch.from_numpy(go.astype(np.float32)).cuda()
+    _, gp_m = g.project_backward(Pt, gm, 32, "fp32")
+    torch.cuda.synchronize()
+    gp_m = gp_m.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gp_m - fp) <= 1e-4 * np.linalg.norm(fp), \
+        np.linalg.norm(gp_m - fp) / np.linalg.norm(fp)
 
 
 def test_batch_256_clouds(orc):
