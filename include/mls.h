@@ -439,10 +439,14 @@ size_t mls_project_backward_workspace_bytes(const mls_grid *grid, int32_t k,
  *                  (OUTLIER: grad_out; NONFINITE query: 0).
  *   grad_points    device, n_points x 3 in `dtype`, overwritten with dL/d p
  *                  for every point of the grid (sum over the queries whose
- *                  list holds the point; 0 for the others). Must be device
- *                  memory from hipMalloc (hardware float atomics).
+ *                  list holds the point; 0 for the others), written once
+ *                  from the sums in the workspace.
  *   workspace      device, at least mls_project_backward_workspace_bytes,
- *                  256-byte aligned; required even when n_queries is 0.
+ *                  256-byte aligned; required even when n_queries is 0. Must
+ *                  be device memory from hipMalloc: the point gradients are
+ *                  summed there in sorted order with hardware float atomics
+ *                  (per-workgroup partial sums in FP64, then one atomic per
+ *                  component and point and workgroup).
  * The summation order of the point gradients follows the hardware order of
  * atomic additions, so they can differ between runs in the last bits; the
  * query gradients are deterministic. Errors: MLS_ERR_INVALID_ARGUMENT for
