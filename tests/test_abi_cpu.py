@@ -112,6 +112,39 @@ def test_project_rejects_bad_arguments_on_host(lib):
     assert lib.mls_grid_destroy(None) == _abi.MLS_ERR_INVALID_ARGUMENT
 
 
+def test_grid_entry_points_reject_a_null_grid(lib):
+    # every call that takes a grid handle refuses a null one on the host,
+    # before anything is launched (no device is needed to see the code)
+    from paper_2401_03365_amd import _abi
+    P = ctypes.c_void_p
+    fake = P(0x100000)
+    bad = _abi.MLS_ERR_INVALID_ARGUMENT
+    prm = _abi.MlsParams(k=8, precision=0, support_radius_h=3.0, min_support=3, stages=0)
+    info = _abi.MlsGridInfo()
+    origin, cell = (ctypes.c_double * 3)(), ctypes.c_double()
+    dims = (ctypes.c_int32 * 3)()
+    p1, p2, p3 = P(), P(), P()
+    cap = ctypes.c_int64()
+    assert lib.mls_rebuild_grid(None, fake, None) == bad
+    assert lib.mls_get_grid_info(None, ctypes.byref(info)) == bad
+    assert lib.mls_get_cloud_grid(None, 0, origin, ctypes.byref(cell), dims) == bad
+    assert lib.mls_grid_sorted_points(None, ctypes.byref(p1), ctypes.byref(p2)) == bad
+    assert lib.mls_grid_cell_table(None, ctypes.byref(p1), ctypes.byref(cap),
+                                   ctypes.byref(p3)) == bad
+    assert lib.mls_project_geometry(None, ctypes.byref(prm), fake, 0, 10, None, fake, fake,
+                                    None, fake, fake, fake, 1 << 20, None) == bad
+    assert lib.mls_project_noalloc(None, ctypes.byref(prm), fake, 0, 10, None, fake, fake,
+                                   None, None) == bad
+    assert lib.mls_project_backward_workspace_bytes(None, 8, 10, 0) == 0
+    # and the tuner refuses null inputs the same way
+    h = (ctypes.c_double * 1)(0.1)
+    cand = (ctypes.c_double * 2)(1.0, 1.25)
+    best = ctypes.c_double()
+    assert lib.mls_autotune_cell(None, 100, None, 1, h, 8, cand, 2, 1, fake, 1 << 20, None,
+                                 ctypes.byref(best), None) == bad
+    assert lib.mls_autotune_workspace_bytes(0, 1, 8, 1) == 0
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     from paper_2401_03365_amd import _abi
     with pytest.raises(RuntimeError, match="not found"):
