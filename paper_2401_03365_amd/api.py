@@ -317,7 +317,7 @@ class Grid:
 
 
 def autotune_cell_factor(points: torch.Tensor, h, k: int, cloud_offsets=None,
-                         candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0),
+                         candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0),
                          stride: int = 1):
     """Measures the neighbour search for each candidate cell edge (factor x
     h) and returns (best factor, {factor: ms}). ``stride`` 1 (the default)
@@ -354,7 +354,7 @@ def size_class(n: int) -> int:
 
 
 def autotune_cells(points: torch.Tensor, h, k: int, cloud_offsets=None,
-                   candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0)):
+                   candidates: Sequence[float] = (0.8, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0)):
     """Cell edge factor per cloud: one factor for a single cloud; for a batch,
     one per cloud-size class (clouds below 20k, 80k, 250k points and above),
     each measured on that class's clouds alone (full searches). Returns
