@@ -174,12 +174,6 @@ def parse():
     return ap.parse_args()
 
 
-def default_cell_factor(k):
-    # edge of the finest grid level in units of h (the search picks coarser
-    # levels where the density needs them)
-    return 1.25
-
-
 class Timer:
     def __init__(self, torch):
         self.torch = torch
@@ -290,16 +284,26 @@ class _Null:
         return False
 
 
+def tuned_cell_factor(api, pts, h, k):
+    """The tuner's cell edge factor for one cloud (full searches of every
+    candidate grid) and its timings."""
+    factors, rep = api.autotune_cells(pts, h, k)
+    return float(factors[0]), rep[0][1]
+
+
 def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label, precision="fp32",
-            keep=None):
+            keep=None, cell_factor=None):
     """fwd (search + fit) and the adjoint of one pass over the whole cloud,
     queries = the cloud's points (FP32 in and out), on the FP32-moment or the
-    FP64 path. The grid is built once; the loss gradient is torch code between
-    the two and is timed apart. value = N / (t_fwd + t_bwd). ``keep``: a dict
-    that receives the forward's outputs and statuses."""
+    FP64 path. The grid is built once (cell edge: ``cell_factor`` x h, else
+    the tuner's pick); the loss gradient is torch code between the two and is
+    timed apart. value = N / (t_fwd + t_bwd). ``keep``: a dict that receives
+    the forward's outputs and statuses."""
     pts = torch.from_numpy(P).cuda()
+    if cell_factor is None:
+        cell_factor, _ = tuned_cell_factor(api, pts, h, k)
     timer = Timer(torch)
-    grid = api.Grid(pts, h, cell_size=default_cell_factor(k) * h)
+    grid = api.Grid(pts, h, cell_size=cell_factor * h)
     out = torch.empty_like(pts)
     status = torch.empty((pts.shape[0],), dtype=torch.uint8, device=pts.device)
 
@@ -324,14 +328,15 @@ def fwd_bwd(api, torch, P, h, k, loss_grad, steps, warmup, label, precision="fp3
     br = {n: timer.ms(n) for n in ("fwd_search", "fwd_fit", "loss_grad", "bwd")}
     t = br["fwd_search"] + br["fwd_fit"] + br["bwd"]
     ok = bool(torch.isfinite(gq).all().item() and torch.isfinite(gp).all().item())
-    log("%s %s: fwd %.2f + %.2f ms, loss %.2f ms, bwd %.2f ms, finite grads %s" %
-        (label, precision, br["fwd_search"], br["fwd_fit"], br["loss_grad"], br["bwd"], ok))
+    log("%s %s (cell %.2f h): fwd %.2f + %.2f ms, loss %.2f ms, bwd %.2f ms, finite grads %s" %
+        (label, precision, cell_factor, br["fwd_search"], br["fwd_fit"], br["loss_grad"],
+         br["bwd"], ok))
     if keep is not None:
         keep["out"], keep["status"] = out, status
     del grid
     return {"value": P.shape[0] / (t / 1000.0), "unit": "pts/s", "n_points": int(P.shape[0]),
-            "k": k, "h": h, "precision": precision, "breakdown_ms": br, "ms_fwd_plus_bwd": t,
-            "grads_finite": ok}
+            "k": k, "h": h, "precision": precision, "cell_factor": cell_factor,
+            "breakdown_ms": br, "ms_fwd_plus_bwd": t, "grads_finite": ok}
 
 
 def sh_sphere_loss(torch, field, P):
@@ -591,12 +596,15 @@ def small_configs(api, torch, keep):
     P2 = synth.torus(1_000_000, sigma=0.005, n_outliers=10_000, seed=2)
     h2 = synth.mean_nn_h(P2)
     for name, P, hh in (("sphere_20k_k32", P1, h1), ("torus_1.01M_k32", P2, h2)):
-        res[name] = {"n_points": int(P.shape[0]), "h": hh}
+        cf, cf_ms = tuned_cell_factor(api, torch.from_numpy(P).cuda(), hh, 32)
+        res[name] = {"n_points": int(P.shape[0]), "h": hh, "cell_factor": cf,
+                     "tuner_search_ms": cf_ms}
         for prec in ("fp64", "fp32"):
-            r, out, st = one_pass(api, torch, P, hh, 32, prec)
+            r, out, st = one_pass(api, torch, P, hh, 32, prec, cell_factor=cf)
             res[name][prec] = r
             keep[(name, prec)] = (P, hh, 32, out, st)
-            log("%s %s: %.3f ms per pass (%.3g pts/s)" % (name, prec, r["ms_per_pass"], r["value"]))
+            log("%s %s (cell %.2f h): %.3f ms per pass (%.3g pts/s)" %
+                (name, prec, cf, r["ms_per_pass"], r["value"]))
     return res
 
 
@@ -969,15 +977,17 @@ def main():
         for prec in ("fp32", "fp64"):
             key = "heightfield_10M_k48" + ("" if prec == "fp32" else "_fp64")
             fb[key] = fwd_bwd(api, torch, P, h, args.k, heightfield_loss(torch, hfield),
-                              args.steps, args.warmup, "fwd+bwd heightfield", precision=prec)
+                              args.steps, args.warmup, "fwd+bwd heightfield", precision=prec,
+                              cell_factor=cf)
         P4, shf = synth.sh_sphere(args.c4_n, sigma=0.005, seed=4, return_field=True)
         h4 = synth.mean_nn_h(P4)
+        cf4, _ = tuned_cell_factor(api, torch.from_numpy(P4).cuda(), h4, 32)
         for prec in ("fp32", "fp64"):
             key = "sh_sphere_2M_k32" + ("" if prec == "fp32" else "_fp64")
             kk = {}
             fb[key] = fwd_bwd(api, torch, P4, h4, 32, sh_sphere_loss(torch, shf, P4),
                               args.steps, args.warmup, "fwd+bwd sh sphere", precision=prec,
-                              keep=kk)
+                              keep=kk, cell_factor=cf4)
             keep[("sh_sphere_2M_k32", prec)] = (P4, h4, 32, kk["out"], kk["status"])
         if not args.no_batch:
             kb = {}
